@@ -1,0 +1,164 @@
+/*
+ * ldpc.h -- C ABI of libldpc.so: syndrome-form flooding sum-product decoding of
+ * quasi-cyclic (QC) LDPC codes on one MI355X (gfx950), in hand-written HIP.
+ *
+ * Method: Algorithm 1 of Milicevic et al., "Key Reconciliation with LDPC Codes
+ * for Long-Distance Quantum Cryptography" (Sec. III-D), applied to the QC
+ * codes of Sec. III-C, in the syndrome (Slepian-Wolf, Sec. II-C.4) form: every
+ * check c carries a target bit s_c, multiplies its outgoing messages by
+ * (-1)^{s_c}, and a frame stops when its hard decisions x satisfy H x = s.
+ *
+ * Conventions shared by every entry point:
+ *  - Status: every function returning int returns LDPC_OK (0) or a negative
+ *    LDPC_E* code; nothing throws across the ABI.  ldpc_last_error() gives a
+ *    human-readable detail of the calling thread's last failure.
+ *  - Memory: pointers named "device" must point into HIP device memory of the
+ *    device the code was created on (e.g. torch CUDA tensors); "host" pointers
+ *    are ordinary host memory.  The caller owns every data buffer and the
+ *    workspace; the library owns only the code handle and its small device
+ *    tables, and performs no device allocation inside ldpc_decode_batch.
+ *  - Streams: decode and syndrome calls are asynchronous on the given
+ *    hipStream_t (NULL = the null stream); outputs are valid after the caller
+ *    synchronises that stream.  Launch errors are reported at enqueue; faults
+ *    inside kernels surface at the caller's synchronisation.
+ *  - Threads: a code handle is immutable after creation and may be used from
+ *    several host threads and streams at once, each call with its own
+ *    workspace and output buffers.
+ */
+#ifndef LDPC_H
+#define LDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LDPC_OK = 0,
+    LDPC_EINVAL = -1,       /* bad argument (null pointer, size, range)          */
+    LDPC_ENOMEM = -2,       /* host or device allocation failed at code creation */
+    LDPC_EDEVICE = -3,      /* HIP runtime error, or wrong current device        */
+    LDPC_EUNSUPPORTED = -4, /* valid code the kernels do not handle (degree cap) */
+    LDPC_EWORKSPACE = -5    /* workspace null, too small or misaligned           */
+};
+
+/* Largest check (row) degree the check-update kernel handles. */
+#define LDPC_MAX_ROW_DEGREE 16
+
+typedef struct ldpc_code ldpc_code;
+
+typedef struct {
+    int32_t n;              /* code length nb*Z                                  */
+    int32_t m;              /* number of checks mb*Z                             */
+    int32_t Z;              /* lifting size (circulant order)                    */
+    int32_t mb, nb;         /* base matrix shape                                 */
+    int32_t blocks;         /* non-zero base entries                             */
+    int64_t edges;          /* Tanner-graph edges, blocks*Z                      */
+    int64_t state_edges;    /* edges on columns of degree >= 2 (stored messages) */
+    int32_t core_cols;      /* base columns of degree >= 2                       */
+    int32_t deg1_cols;      /* base columns of degree 1                          */
+    int32_t deg0_cols;      /* base columns of degree 0                          */
+    int32_t max_row_degree; /* largest number of non-zero blocks in a base row   */
+} ldpc_code_info_t;
+
+/*
+ * Create a QC code from its base matrix (Sec. III-C): each non-zero entry is a
+ * Z x Z circulant permutation, the identity with every row cyclically shifted
+ * right by the entry (0-based; the paper's I_i is shift i-1), so row a of
+ * block (r, c) joins check r*Z + a to variable c*Z + ((a + shift) mod Z).
+ *   mb, nb  base shape, >= 1
+ *   base    host, mb*nb int32 row-major; -1 = zero block, else shift in [0, Z)
+ *   Z       lifting size, 1 <= Z, with nb*Z and mb*Z < 2^31
+ *   out     host; receives the handle (set to NULL on failure)
+ * Builds the block tables (row lists, column lists, degree classes) and copies
+ * them to the current HIP device, to which the handle is bound.
+ * Errors: LDPC_EINVAL (shape, shift range, null), LDPC_EUNSUPPORTED (a row of
+ * degree > LDPC_MAX_ROW_DEGREE, a row with no block, or more than 65535 base
+ * rows or columns of degree >= 2), LDPC_ENOMEM, LDPC_EDEVICE.
+ */
+int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldpc_code **out);
+
+/* Release a handle and its device tables; NULL is ignored.  The caller must
+ * ensure no enqueued call using the handle is still running. */
+void ldpc_code_destroy(ldpc_code *code);
+
+/* Sizes and degree classes of a code.  out: host.  LDPC_EINVAL on null. */
+int ldpc_code_info(const ldpc_code *code, ldpc_code_info_t *out);
+
+typedef struct {
+    int32_t early_stop;      /* 1: a frame stops at the first checked iteration whose
+                                decisions satisfy H x = s (Alg. 1 Step 4); 0: every
+                                frame runs max_iters iterations                      */
+    int32_t check_from_iter; /* the check runs only at iterations t >= this value (the
+                                paper's early-termination lookup, Sec. IV-A); 0 = from
+                                t = 0, i.e. also on the channel decisions            */
+    int32_t msg_fp16;        /* 1: check-to-variable messages stored as IEEE half;
+                                all arithmetic and sums stay in float32             */
+    int32_t reserved;        /* must be 0                                          */
+    float *llr_out;          /* optional device [F][n]: posterior L_v at exit      */
+    void **timing_events;    /* optional host array of caller-created hipEvent_t
+                                handles, recorded on the decode stream around the
+                                iteration kernels: event 2(t-1) before the check
+                                pass of iteration t, 2(t-1)+1 before its variable
+                                pass, 2T after the last variable pass             */
+    int32_t n_timing_events; /* >= 2*max_iters + 1 when timing_events is set      */
+} ldpc_decode_opts;
+
+/* Fill opts with the defaults {early_stop=1, check_from_iter=0, msg_fp16=0,
+ * reserved=0, llr_out=NULL, timing_events=NULL, n_timing_events=0}. */
+void ldpc_decode_opts_init(ldpc_decode_opts *opts);
+
+/* Workspace bytes ldpc_decode_batch needs for F frames and max_iters iterations
+ * with these options (NULL = defaults).  Returns 0 on an invalid argument. */
+size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
+                            const ldpc_decode_opts *opts);
+
+/*
+ * Decode F frames (Alg. 1, Steps 2-4, flooding schedule, syndrome form).
+ *   llr        device [F][n] float32: channel LLR Q_v = ln P(x_v=0)/P(x_v=1)
+ *              (Step 1 is done by the caller), frame-major, v = c*Z + j
+ *   syndrome   device [F][m] uint8: target bits s_c in {0,1}, c = r*Z + a
+ *   max_iters  T >= 0: most iterations per frame
+ *   bits_out   device [F][n] uint8: hard decisions x_v = [L_v < 0] at exit
+ *   iters_out  device [F] int32: iterations completed at exit; a frame whose
+ *              channel decisions already satisfy H x = s reports 0
+ *   converged_out device [F] uint8: 1 iff H x = s holds for bits_out
+ *   opts       host, NULL = defaults (see ldpc_decode_opts)
+ *   workspace  device, >= ldpc_workspace_bytes(code, F, max_iters, opts) bytes,
+ *              256-byte aligned; its contents on entry are ignored
+ *   stream     hipStream_t or NULL
+ * Messages are clamped through the Phi argument range [1e-7, 30].  Frames are
+ * independent: frame f's outputs depend only on frame f's inputs, bit for bit,
+ * whatever F and the other frames are.
+ * Errors: LDPC_EINVAL (F < 1, max_iters < 0, check_from_iter < 0, null
+ * pointer, reserved != 0, too few timing events), LDPC_EWORKSPACE, LDPC_EDEVICE (current device is
+ * not the code's device, or a launch failed).
+ */
+int ldpc_decode_batch(const ldpc_code *code, int32_t F,
+                      const float *llr, const uint8_t *syndrome, int32_t max_iters,
+                      uint8_t *bits_out, int32_t *iters_out, uint8_t *converged_out,
+                      const ldpc_decode_opts *opts, void *workspace, size_t workspace_bytes,
+                      void *stream);
+
+/*
+ * s = H x mod 2 for F words.
+ *   bits     device [F][n] uint8 (only bit 0 of each byte is used)
+ *   syn_out  device [F][m] uint8, values 0/1
+ * Errors: LDPC_EINVAL, LDPC_EDEVICE.
+ */
+int ldpc_syndrome(const ldpc_code *code, int32_t F, const uint8_t *bits, uint8_t *syn_out,
+                  void *stream);
+
+/* Static English text for a status code. */
+const char *ldpc_status_string(int status);
+
+/* Detail of the calling thread's most recent failure ("" if none). */
+const char *ldpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDPC_H */

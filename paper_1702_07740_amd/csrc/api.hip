@@ -1,0 +1,326 @@
+// C ABI of libldpc.so (declared in include/ldpc.h): argument checking, code
+// tables, workspace sizing, and the enqueue of the decoder kernels.
+#include "../../include/ldpc.h"
+#include "internal.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using ldpc::CodeDev;
+
+struct ldpc_code {
+    ldpc_code_info_t info;
+    int device;
+    CodeDev dev;            // sizes + device table pointers
+    int32_t *table;         // one device allocation holding every table
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail_with(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail_with(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int check_device(const ldpc_code *code) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev != code->device)
+        return fail_with(LDPC_EDEVICE, "current device %d is not the code's device %d", dev,
+                         code->device);
+    return LDPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ldpc_status_string(int status) {
+    switch (status) {
+        case LDPC_OK: return "ok";
+        case LDPC_EINVAL: return "invalid argument";
+        case LDPC_ENOMEM: return "out of memory";
+        case LDPC_EDEVICE: return "HIP device error";
+        case LDPC_EUNSUPPORTED: return "unsupported code";
+        case LDPC_EWORKSPACE: return "workspace missing, too small or misaligned";
+        default: return "unknown status";
+    }
+}
+
+const char *ldpc_last_error(void) { return g_last_error.c_str(); }
+
+void ldpc_decode_opts_init(ldpc_decode_opts *o) {
+    if (!o) return;
+    o->early_stop = 1;
+    o->check_from_iter = 0;
+    o->msg_fp16 = 0;
+    o->reserved = 0;
+    o->llr_out = nullptr;
+    o->timing_events = nullptr;
+    o->n_timing_events = 0;
+}
+
+int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldpc_code **out) {
+    if (!out) return fail_with(LDPC_EINVAL, "out is null");
+    *out = nullptr;
+    if (!base) return fail_with(LDPC_EINVAL, "base is null");
+    if (mb < 1 || nb < 1 || Z < 1) return fail_with(LDPC_EINVAL, "mb, nb, Z must be >= 1");
+    if ((int64_t)nb * Z >= (1ll << 31) || (int64_t)mb * Z >= (1ll << 31))
+        return fail_with(LDPC_EINVAL, "code too long: nb*Z and mb*Z must be < 2^31");
+
+    // column degrees and classes
+    std::vector<int32_t> col_deg(nb, 0);
+    for (int r = 0; r < mb; ++r)
+        for (int c = 0; c < nb; ++c) {
+            const int32_t s = base[(size_t)r * nb + c];
+            if (s < -1 || s >= Z)
+                return fail_with(LDPC_EINVAL, "base[%d][%d] = %d is outside [-1, Z)", r, c, s);
+            if (s >= 0) col_deg[c]++;
+        }
+    std::vector<int32_t> col_kind(nb), col_ref(nb);
+    std::vector<int32_t> core_col, d1_col;
+    for (int c = 0; c < nb; ++c) {
+        if (col_deg[c] >= 2) {
+            col_kind[c] = ldpc::COL_CORE;
+            col_ref[c] = (int32_t)core_col.size();
+            core_col.push_back(c);
+        } else if (col_deg[c] == 1) {
+            col_kind[c] = ldpc::COL_DEG1;
+            col_ref[c] = (int32_t)d1_col.size();
+            d1_col.push_back(c);
+        } else {
+            col_kind[c] = ldpc::COL_DEG0;
+            col_ref[c] = -1;
+        }
+    }
+    // blocks in row-major order; state blocks numbered in that order
+    std::vector<int32_t> row_first(mb), row_deg(mb);
+    std::vector<int32_t> blk_shift, blk_kind, blk_ref, blk_col, blk_core;
+    std::vector<int32_t> d1_shift(d1_col.size(), 0);
+    std::vector<int32_t> st_row, st_core, st_shift;
+    int maxdeg = 0;
+    for (int r = 0; r < mb; ++r) {
+        row_first[r] = (int32_t)blk_shift.size();
+        int d = 0;
+        for (int c = 0; c < nb; ++c) {
+            const int32_t s = base[(size_t)r * nb + c];
+            if (s < 0) continue;
+            ++d;
+            blk_shift.push_back(s);
+            blk_col.push_back(c);
+            if (col_kind[c] == ldpc::COL_CORE) {
+                blk_kind.push_back(ldpc::KIND_STATE);
+                blk_ref.push_back((int32_t)st_row.size());
+                blk_core.push_back(col_ref[c]);
+                st_row.push_back(r);
+                st_core.push_back(col_ref[c]);
+                st_shift.push_back(s);
+            } else {
+                blk_kind.push_back(ldpc::KIND_DEG1);
+                blk_ref.push_back(col_ref[c]);
+                blk_core.push_back(-1);
+                d1_shift[col_ref[c]] = s;
+            }
+        }
+        row_deg[r] = d;
+        if (d == 0) return fail_with(LDPC_EUNSUPPORTED, "base row %d has no block", r);
+        if (d > LDPC_MAX_ROW_DEGREE)
+            return fail_with(LDPC_EUNSUPPORTED, "base row %d has degree %d > %d", r, d,
+                             LDPC_MAX_ROW_DEGREE);
+        if (d > maxdeg) maxdeg = d;
+    }
+    const int NS = (int)st_row.size(), NC = (int)core_col.size(), ND1 = (int)d1_col.size();
+    if (mb > 65535 || NC > 65535)  // base rows and core columns index grid.y
+        return fail_with(LDPC_EUNSUPPORTED, "more than 65535 base rows or core columns");
+    // per core column: its state blocks in increasing row order
+    std::vector<int32_t> core_first(NC), core_deg(NC, 0), core_state(NS), core_shift(NS);
+    for (int i = 0; i < NS; ++i) core_deg[st_core[i]]++;
+    for (int k = 0, acc = 0; k < NC; ++k) {
+        core_first[k] = acc;
+        acc += core_deg[k];
+    }
+    {
+        std::vector<int32_t> fill(NC, 0);
+        for (int i = 0; i < NS; ++i) {  // i runs in row-major order, so rows increase
+            const int k = st_core[i];
+            core_state[core_first[k] + fill[k]] = i;
+            core_shift[core_first[k] + fill[k]] = st_shift[i];
+            fill[k]++;
+        }
+    }
+
+    // one device allocation for every table
+    const int B = (int)blk_shift.size();
+    std::vector<int32_t> host;
+    auto put = [&](const std::vector<int32_t> &v) {
+        const size_t off = host.size();
+        host.insert(host.end(), v.begin(), v.end());
+        host.push_back(0);  // keeps every table non-empty
+        return off;
+    };
+    const size_t o_row_first = put(row_first), o_row_deg = put(row_deg);
+    const size_t o_bs = put(blk_shift), o_bk = put(blk_kind), o_br = put(blk_ref),
+                 o_bc = put(blk_col), o_bco = put(blk_core);
+    const size_t o_cc = put(core_col), o_cf = put(core_first), o_cd = put(core_deg),
+                 o_cs = put(core_state), o_csh = put(core_shift);
+    const size_t o_colk = put(col_kind), o_colr = put(col_ref), o_d1s = put(d1_shift);
+
+    ldpc_code *code = new (std::nothrow) ldpc_code();
+    if (!code) return fail_with(LDPC_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&code->device);
+    if (e != hipSuccess) {
+        delete code;
+        return fail_with(LDPC_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    e = hipMalloc(reinterpret_cast<void **>(&code->table), host.size() * sizeof(int32_t));
+    if (e != hipSuccess) {
+        delete code;
+        return fail_with(e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EDEVICE, "hipMalloc: %s",
+                         hipGetErrorString(e));
+    }
+    e = hipMemcpy(code->table, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(code->table);
+        delete code;
+        return fail_with(LDPC_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+    const int32_t *T = code->table;
+    CodeDev &d = code->dev;
+    d.Z = Z;
+    d.mb = mb;
+    d.nb = nb;
+    d.n = nb * Z;
+    d.m = mb * Z;
+    d.NS = NS;
+    d.NC = NC;
+    d.ND1 = ND1;
+    d.W = (Z + 63) / 64;
+    d.row_first = T + o_row_first;
+    d.row_deg = T + o_row_deg;
+    d.blk_shift = T + o_bs;
+    d.blk_kind = T + o_bk;
+    d.blk_ref = T + o_br;
+    d.blk_col = T + o_bc;
+    d.blk_core = T + o_bco;
+    d.core_col = T + o_cc;
+    d.core_first = T + o_cf;
+    d.core_deg = T + o_cd;
+    d.core_state = T + o_cs;
+    d.core_shift = T + o_csh;
+    d.col_kind = T + o_colk;
+    d.col_ref = T + o_colr;
+    d.d1_shift = T + o_d1s;
+
+    ldpc_code_info_t &I = code->info;
+    I.n = d.n;
+    I.m = d.m;
+    I.Z = Z;
+    I.mb = mb;
+    I.nb = nb;
+    I.blocks = B;
+    I.edges = (int64_t)B * Z;
+    I.state_edges = (int64_t)NS * Z;
+    I.core_cols = NC;
+    I.deg1_cols = ND1;
+    I.deg0_cols = nb - NC - ND1;
+    I.max_row_degree = maxdeg;
+    *out = code;
+    return LDPC_OK;
+}
+
+void ldpc_code_destroy(ldpc_code *code) {
+    if (!code) return;
+    if (code->table) (void)hipFree(code->table);
+    delete code;
+}
+
+int ldpc_code_info(const ldpc_code *code, ldpc_code_info_t *out) {
+    if (!code || !out) return fail_with(LDPC_EINVAL, "null argument");
+    *out = code->info;
+    return LDPC_OK;
+}
+
+size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
+                            const ldpc_decode_opts *opts) {
+    if (!code || F < 1 || max_iters < 0) return 0;
+    ldpc_decode_opts o;
+    ldpc_decode_opts_init(&o);
+    if (opts) o = *opts;
+    return ldpc::work_layout(code->dev, F, max_iters, o.msg_fp16 != 0, o.llr_out != nullptr).total;
+}
+
+int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const uint8_t *syndrome,
+                      int32_t max_iters, uint8_t *bits_out, int32_t *iters_out,
+                      uint8_t *converged_out, const ldpc_decode_opts *opts, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+    if (!code) return fail_with(LDPC_EINVAL, "code is null");
+    if (F < 1 || F > 65535) return fail_with(LDPC_EINVAL, "F = %d outside [1, 65535]", F);
+    if (max_iters < 0) return fail_with(LDPC_EINVAL, "max_iters = %d < 0", max_iters);
+    if (!llr || !syndrome || !bits_out || !iters_out || !converged_out)
+        return fail_with(LDPC_EINVAL, "null input or output pointer");
+    ldpc_decode_opts o;
+    ldpc_decode_opts_init(&o);
+    if (opts) o = *opts;
+    if (o.reserved != 0) return fail_with(LDPC_EINVAL, "opts.reserved must be 0");
+    if (o.check_from_iter < 0) return fail_with(LDPC_EINVAL, "check_from_iter < 0");
+    if (o.timing_events && o.n_timing_events < 2 * max_iters + 1)
+        return fail_with(LDPC_EINVAL, "%d timing events; need 2*max_iters + 1 = %d",
+                         o.n_timing_events, 2 * max_iters + 1);
+    if ((int64_t)(max_iters + 1) * F >= (1ll << 31))
+        return fail_with(LDPC_EINVAL, "(max_iters + 1) * F too large");
+    const size_t need = ldpc::work_layout(code->dev, F, max_iters, o.msg_fp16 != 0,
+                                          o.llr_out != nullptr).total;
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return fail_with(LDPC_EWORKSPACE, "workspace %p of %zu bytes; need %zu bytes, 256-aligned",
+                         workspace, workspace_bytes, need);
+    int st = check_device(code);
+    if (st != LDPC_OK) return st;
+
+    ldpc::DecodeLaunch l{};
+    l.c = code->dev;
+    l.F = F;
+    l.T = max_iters;
+    l.early_stop = o.early_stop ? 1 : 0;
+    l.check_from = o.check_from_iter;
+    l.fp16 = o.msg_fp16 ? 1 : 0;
+    l.llr = llr;
+    l.syndrome = syndrome;
+    l.bits_out = bits_out;
+    l.iters_out = iters_out;
+    l.conv_out = converged_out;
+    l.llr_out = o.llr_out;
+    l.ws = static_cast<char *>(workspace);
+    l.events = reinterpret_cast<hipEvent_t *>(o.timing_events);
+    l.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = ldpc::enqueue_decode(l);
+    if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+int ldpc_syndrome(const ldpc_code *code, int32_t F, const uint8_t *bits, uint8_t *syn_out,
+                  void *stream) {
+    if (!code) return fail_with(LDPC_EINVAL, "code is null");
+    if (F < 1 || F > 65535) return fail_with(LDPC_EINVAL, "F = %d outside [1, 65535]", F);
+    if (!bits || !syn_out) return fail_with(LDPC_EINVAL, "null pointer");
+    int st = check_device(code);
+    if (st != LDPC_OK) return st;
+    hipError_t e = ldpc::enqueue_syndrome(code->dev, F, bits, syn_out,
+                                          static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,468 @@
+// Flooding sum-product decoding of QC LDPC codes in syndrome form, gfx950.
+//
+// One decode is a short sequence of launches on the caller's stream:
+//   init      fail flags, packed syndrome bits, core totals L = Q
+//   t = 1..T  check pass (Alg. 1 Step 2, plus the Step 4 check of iteration
+//             t-1) and variable pass (Step 3, core columns)
+//   vote      the Step 4 check of the last iteration
+//   finalize  hard decisions, posteriors, iteration counts
+//
+// Edge state.  Messages live per non-zero base block as one array of Z values
+// in check order: block (r, c) with shift s holds m(r*Z + a -> c*Z + (a+s)%Z)
+// at index a.  The check pass reads and writes each array contiguously; the
+// variable pass reads block (r, c) at index (j - s) mod Z, contiguous with one
+// wrap.  No index arrays exist: the circulant shift is the whole addressing.
+//
+// Degree-1 columns (the long diagonal, Sec. III-C) keep no state: their
+// variable-to-check message is the constant channel LLR, and their posterior
+// Q + m is formed in the check pass only for the decision bit, which is stored
+// packed by check position (one bit per degree-1 block and check).
+//
+// Early stop.  Frame f's check for iteration t-1 is evaluated inside check
+// pass t from values that pass gathers anyway (core totals of iteration t-1 and
+// degree-1 decision bits of iteration t-1), and written to fail[t-1][f].  Every
+// pass skips a frame whose earlier check succeeded; the variable pass t skips
+// a frame whose check at t-1 succeeded, so the frame's totals and degree-1 bits
+// stay those of its exit iteration.
+#include "internal.h"
+
+#include <hip/hip_fp16.h>
+
+namespace ldpc {
+
+namespace {
+
+constexpr int kBlock = 256;  // threads per workgroup: 4 wave64s
+constexpr float kPhiLo = 1e-7f;
+constexpr float kPhiHi = 30.0f;
+
+// Phi(x) = -ln tanh(x/2) on the clamped argument, evaluated as
+// log1p(2 / expm1(x)) so that large x keeps full relative precision.
+__device__ __forceinline__ float phi_f32(float x) {
+    x = fminf(fmaxf(x, kPhiLo), kPhiHi);
+    return log1pf(2.0f / expm1f(x));
+}
+
+template <typename Msg> __device__ __forceinline__ float msg_load(const Msg *p);
+template <> __device__ __forceinline__ float msg_load<float>(const float *p) { return *p; }
+template <> __device__ __forceinline__ float msg_load<_Float16>(const _Float16 *p) {
+    return static_cast<float>(*p);
+}
+template <typename Msg> __device__ __forceinline__ void msg_store(Msg *p, float v);
+template <> __device__ __forceinline__ void msg_store<float>(float *p, float v) { *p = v; }
+template <> __device__ __forceinline__ void msg_store<_Float16>(_Float16 *p, float v) {
+    *p = static_cast<_Float16>(v);
+}
+
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
+
+struct CnArgs {
+    const float *llr;          // [F][n]
+    void *msg;                 // [F][NS][Z] messages (float or half)
+    const float *tot;          // [F][NC][Z] core totals of iteration t-1
+    const uint64_t *d1_prev;   // [F][ND1][W] degree-1 decision bits of iteration t-1
+    uint64_t *d1_cur;          // [F][ND1][W] degree-1 decision bits of iteration t
+    const uint64_t *synbits;   // [F][mb][W]
+    int32_t *fail;             // [T+1][F]
+    float *d1post;             // [F][ND1][Z] degree-1 posteriors of iteration t, or null
+    size_t msg_frame, tot_frame, d1_frame, syn_frame, d1post_frame;
+    int F, t;
+    int update;                // 1: compute the messages of iteration t
+    int first;                 // 1: t == 1, all stored messages are zero
+    int vote;                  // 1: evaluate the check of iteration t-1 (or t, vote-only)
+    int d1_from_llr;           // 1: the voted iteration is 0, decisions come from Q
+    int skip_after;            // frame inactive if fail[skip_after][f] == 0 (-1: never)
+};
+
+// One check (r, a) of one frame, row degree D.  `valid` is false for the
+// padding lanes a >= Z of the last tile; they take part in the wave ballots
+// with zero bits and touch no memory.
+template <int D, typename Msg>
+__device__ __forceinline__ void check_update(const CodeDev &c, const CnArgs &A, int f, int r,
+                                             int a, bool valid) {
+    const int Z = c.Z;
+    const int b0 = c.row_first[r];
+    const float *llr = A.llr + (size_t)f * c.n;
+    const float *tot = A.tot + (size_t)f * A.tot_frame;
+    Msg *msg = reinterpret_cast<Msg *>(A.msg) + (size_t)f * A.msg_frame;
+    const int w = a >> 6;
+    const int bit = a & 63;
+
+    float x[D];         // variable-to-check inputs L_vc of iteration t-1
+    int vpar = 0;       // parity of the iteration t-1 decisions on this check
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int b = b0 + k;
+        const int s = c.blk_shift[b];
+        int j = a + s;
+        j -= (j >= Z) ? Z : 0;
+        float xv = 1.0f;
+        int dec = 0;
+        if (c.blk_kind[b] == KIND_STATE) {
+            if (valid) {
+                const float lt = tot[(size_t)c.blk_core[b] * Z + j];
+                dec = lt < 0.0f;
+                float mo = 0.0f;
+                if (A.update && !A.first) mo = msg_load<Msg>(msg + (size_t)c.blk_ref[b] * Z + a);
+                xv = lt - mo;
+            }
+        } else {
+            if (valid) {
+                xv = llr[(size_t)c.blk_col[b] * Z + j];
+                if (A.vote) {
+                    if (A.d1_from_llr) {
+                        dec = xv < 0.0f;
+                    } else {
+                        const uint64_t wd =
+                            A.d1_prev[(size_t)f * A.d1_frame + (size_t)c.blk_ref[b] * c.W + w];
+                        dec = (int)((wd >> bit) & 1ull);
+                    }
+                }
+            }
+        }
+        x[k] = xv;
+        vpar ^= dec;
+    }
+
+    if (A.vote) {
+        int sbit = 0;
+        if (valid) sbit = (int)((A.synbits[(size_t)f * A.syn_frame + (size_t)r * c.W + w] >> bit) & 1ull);
+        const unsigned long long bad = wave_ballot(valid && (vpar ^ sbit));
+        if (bad != 0ull && (threadIdx.x & 63) == 0)
+            __hip_atomic_store(A.fail + (size_t)(A.update ? A.t - 1 : A.t) * A.F + f, 1,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!A.update) return;
+
+    // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums.
+    float ph[D];
+    int neg = 0;
+    int par = 0;
+    if (valid) par = (int)((A.synbits[(size_t)f * A.syn_frame + (size_t)r * c.W + w] >> bit) & 1ull);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int nk = x[k] < 0.0f;
+        neg |= nk << k;
+        par ^= nk;
+        ph[k] = phi_f32(fabsf(x[k]));
+    }
+    float pre[D];
+    pre[0] = 0.0f;
+#pragma unroll
+    for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + ph[k - 1];
+    float suf = 0.0f;
+    float out[D];
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) {
+        const float mag = phi_f32(pre[k] + suf);
+        suf += ph[k];
+        out[k] = ((par ^ (neg >> k)) & 1) ? -mag : mag;
+    }
+
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int b = b0 + k;
+        if (c.blk_kind[b] == KIND_STATE) {
+            if (valid) msg_store<Msg>(msg + (size_t)c.blk_ref[b] * Z + a, out[k]);
+        } else {
+            const float lp = x[k] + out[k];  // posterior of the degree-1 variable
+            const unsigned long long bits = wave_ballot(valid && lp < 0.0f);
+            const int ref = c.blk_ref[b];
+            if ((threadIdx.x & 63) == 0 && a < Z)
+                A.d1_cur[(size_t)f * A.d1_frame + (size_t)ref * c.W + w] = bits;
+            if (A.d1post && valid) A.d1post[(size_t)f * A.d1post_frame + (size_t)ref * Z + a] = lp;
+        }
+    }
+}
+
+template <typename Msg>
+__global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A) {
+    const int f = blockIdx.z;
+    const int r = blockIdx.y;
+    if (A.skip_after >= 0 && A.fail[(size_t)A.skip_after * A.F + f] == 0) return;
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = a < c.Z;
+    switch (c.row_deg[r]) {
+#define LDPC_CASE(D) \
+    case D: check_update<D, Msg>(c, A, f, r, a, valid); break;
+        LDPC_CASE(1) LDPC_CASE(2) LDPC_CASE(3) LDPC_CASE(4) LDPC_CASE(5) LDPC_CASE(6)
+        LDPC_CASE(7) LDPC_CASE(8) LDPC_CASE(9) LDPC_CASE(10) LDPC_CASE(11) LDPC_CASE(12)
+        LDPC_CASE(13) LDPC_CASE(14) LDPC_CASE(15) LDPC_CASE(16)
+#undef LDPC_CASE
+        default: break;
+    }
+}
+
+struct VnArgs {
+    const float *llr;
+    const void *msg;
+    float *tot;
+    const int32_t *fail;
+    size_t msg_frame, tot_frame;
+    int F, t;
+};
+
+// Step 3 for the core columns: L_v = Q_v + sum of the column's messages, in
+// increasing row order.  One thread per (core column, position j).
+template <typename Msg>
+__global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A) {
+    const int f = blockIdx.z;
+    const int k = blockIdx.y;
+    if (A.fail[(size_t)(A.t - 1) * A.F + f] == 0) return;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int Z = c.Z;
+    if (j >= Z) return;
+    const Msg *msg = reinterpret_cast<const Msg *>(A.msg) + (size_t)f * A.msg_frame;
+    float L = A.llr[(size_t)f * c.n + (size_t)c.core_col[k] * Z + j];
+    const int i0 = c.core_first[k], deg = c.core_deg[k];
+    for (int i = 0; i < deg; ++i) {
+        int idx = j - c.core_shift[i0 + i];
+        idx += (idx < 0) ? Z : 0;
+        L += msg_load<Msg>(msg + (size_t)c.core_state[i0 + i] * Z + idx);
+    }
+    A.tot[(size_t)f * A.tot_frame + (size_t)k * Z + j] = L;
+}
+
+// fail[t][f] = 1 marks "iteration t not checked or check failed".
+__global__ void init_fail(int32_t *fail, int F, int T, int early_stop, int check_from) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (T + 1) * F) return;
+    const int t = i / F;
+    const bool checked = (t == T) || (early_stop && t >= check_from);
+    fail[i] = checked ? 0 : 1;
+}
+
+// Pack the syndrome bytes into 64-bit words per base row: bit a%64 of word a/64.
+__global__ __launch_bounds__(kBlock) void pack_syndrome(CodeDev c, const uint8_t *syn,
+                                                        uint64_t *synbits, size_t syn_frame) {
+    const int f = blockIdx.z, r = blockIdx.y;
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = a < c.Z;
+    const int v = valid ? (syn[(size_t)f * c.m + (size_t)r * c.Z + a] & 1) : 0;
+    const unsigned long long bits = wave_ballot(v != 0);
+    if ((threadIdx.x & 63) == 0 && valid)
+        synbits[(size_t)f * syn_frame + (size_t)r * c.W + (a >> 6)] = bits;
+}
+
+// Core totals of iteration 0: L_v = Q_v.
+__global__ __launch_bounds__(kBlock) void init_totals(CodeDev c, const float *llr, float *tot,
+                                                      size_t tot_frame) {
+    const int f = blockIdx.z, k = blockIdx.y;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= c.Z) return;
+    tot[(size_t)f * tot_frame + (size_t)k * c.Z + j] =
+        llr[(size_t)f * c.n + (size_t)c.core_col[k] * c.Z + j];
+}
+
+struct FinArgs {
+    const float *llr;
+    const float *tot;
+    const uint64_t *d1bits[2];
+    const float *d1post[2];
+    const int32_t *fail;
+    uint8_t *bits_out;
+    int32_t *iters_out;
+    uint8_t *conv_out;
+    float *llr_out;
+    size_t tot_frame, d1_frame, d1post_frame;
+    int F, T;
+};
+
+__global__ __launch_bounds__(kBlock) void finalize(CodeDev c, FinArgs A) {
+    const int f = blockIdx.y;
+    int it = A.T, conv = 0;
+    for (int t = 0; t <= A.T; ++t)
+        if (A.fail[(size_t)t * A.F + f] == 0) {
+            it = t;
+            conv = 1;
+            break;
+        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.iters_out[f] = it;
+        A.conv_out[f] = (uint8_t)conv;
+    }
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= c.n) return;
+    const int Z = c.Z;
+    const int col = v / Z;
+    const int j = v - col * Z;
+    const int kind = c.col_kind[col], ref = c.col_ref[col];
+    const float q = A.llr[(size_t)f * c.n + v];
+    float L = q;
+    int bit = q < 0.0f;
+    if (kind == COL_CORE) {
+        L = A.tot[(size_t)f * A.tot_frame + (size_t)ref * Z + j];
+        bit = L < 0.0f;
+    } else if (kind == COL_DEG1 && it > 0) {
+        int a = j - c.d1_shift[ref];
+        a += (a < 0) ? Z : 0;
+        const uint64_t wd = A.d1bits[it & 1][(size_t)f * A.d1_frame + (size_t)ref * c.W + (a >> 6)];
+        bit = (int)((wd >> (a & 63)) & 1ull);
+        if (A.llr_out) L = A.d1post[it & 1][(size_t)f * A.d1post_frame + (size_t)ref * Z + a];
+    }
+    A.bits_out[(size_t)f * c.n + v] = (uint8_t)bit;
+    if (A.llr_out) A.llr_out[(size_t)f * c.n + v] = L;
+}
+
+__global__ __launch_bounds__(kBlock) void syndrome_kernel(CodeDev c, const uint8_t *bits,
+                                                          uint8_t *syn) {
+    const int f = blockIdx.z, r = blockIdx.y;
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= c.Z) return;
+    const uint8_t *x = bits + (size_t)f * c.n;
+    const int b0 = c.row_first[r], d = c.row_deg[r];
+    int p = 0;
+    for (int k = 0; k < d; ++k) {
+        int j = a + c.blk_shift[b0 + k];
+        j -= (j >= c.Z) ? c.Z : 0;
+        p ^= x[(size_t)c.blk_col[b0 + k] * c.Z + j] & 1;
+    }
+    syn[(size_t)f * c.m + (size_t)r * c.Z + a] = (uint8_t)p;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline unsigned tiles(int n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename Msg>
+hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
+    const CodeDev &c = l.c;
+    const int F = l.F, T = l.T;
+    char *ws = l.ws;
+    void *msg = ws + L.msg;
+    float *tot = reinterpret_cast<float *>(ws + L.tot);
+    uint64_t *d1b[2] = {reinterpret_cast<uint64_t *>(ws + L.d1bits),
+                        reinterpret_cast<uint64_t *>(ws + L.d1bits) + (size_t)F * L.d1bits_frame};
+    uint64_t *synbits = reinterpret_cast<uint64_t *>(ws + L.synbits);
+    int32_t *fail = reinterpret_cast<int32_t *>(ws + L.fail);
+    float *d1p[2] = {nullptr, nullptr};
+    if (l.llr_out) {
+        d1p[0] = reinterpret_cast<float *>(ws + L.d1post);
+        d1p[1] = d1p[0] + (size_t)F * L.d1post_frame;
+    }
+    hipStream_t st = l.stream;
+
+    const int nfail = (T + 1) * F;
+    init_fail<<<dim3((nfail + kBlock - 1) / kBlock), dim3(kBlock), 0, st>>>(fail, F, T, l.early_stop,
+                                                                           l.check_from);
+    pack_syndrome<<<dim3(tiles(c.Z), c.mb, F), dim3(kBlock), 0, st>>>(c, l.syndrome, synbits,
+                                                                     L.synbits_frame);
+    if (c.NC > 0)
+        init_totals<<<dim3(tiles(c.Z), c.NC, F), dim3(kBlock), 0, st>>>(c, l.llr, tot, L.tot_frame);
+
+    auto checked = [&](int t) { return t == T || (l.early_stop && t >= l.check_from); };
+
+    CnArgs a{};
+    a.llr = l.llr;
+    a.msg = msg;
+    a.tot = tot;
+    a.synbits = synbits;
+    a.fail = fail;
+    a.msg_frame = L.msg_frame;
+    a.tot_frame = L.tot_frame;
+    a.d1_frame = L.d1bits_frame;
+    a.syn_frame = L.synbits_frame;
+    a.d1post_frame = L.d1post_frame;
+    a.F = F;
+    const dim3 cn_grid(tiles(c.Z), c.mb, F);
+
+    VnArgs v{};
+    v.llr = l.llr;
+    v.msg = msg;
+    v.tot = tot;
+    v.fail = fail;
+    v.msg_frame = L.msg_frame;
+    v.tot_frame = L.tot_frame;
+    v.F = F;
+    const dim3 vn_grid(tiles(c.Z), c.NC, F);
+
+    for (int t = 1; t <= T; ++t) {
+        a.t = t;
+        a.update = 1;
+        a.first = (t == 1);
+        a.vote = checked(t - 1) ? 1 : 0;
+        a.d1_from_llr = (t == 1);
+        a.d1_prev = d1b[(t - 1) & 1];
+        a.d1_cur = d1b[t & 1];
+        a.d1post = d1p[t & 1];
+        a.skip_after = t >= 2 ? t - 2 : -1;
+        if (l.events) (void)hipEventRecord(l.events[2 * (t - 1)], st);
+        check_pass<Msg><<<cn_grid, dim3(kBlock), 0, st>>>(c, a);
+        if (l.events) (void)hipEventRecord(l.events[2 * (t - 1) + 1], st);
+        if (c.NC > 0) {
+            v.t = t;
+            variable_pass<Msg><<<vn_grid, dim3(kBlock), 0, st>>>(c, v);
+        }
+    }
+    if (l.events) (void)hipEventRecord(l.events[2 * T], st);
+    // the check of the last iteration (or of the channel decisions when T = 0)
+    a.t = T;
+    a.update = 0;
+    a.first = 0;
+    a.vote = 1;
+    a.d1_from_llr = (T == 0);
+    a.d1_prev = d1b[T & 1];
+    a.d1_cur = nullptr;
+    a.d1post = nullptr;
+    a.skip_after = T >= 1 ? T - 1 : -1;
+    check_pass<Msg><<<cn_grid, dim3(kBlock), 0, st>>>(c, a);
+
+    FinArgs fa{};
+    fa.llr = l.llr;
+    fa.tot = tot;
+    fa.d1bits[0] = d1b[0];
+    fa.d1bits[1] = d1b[1];
+    fa.d1post[0] = d1p[0];
+    fa.d1post[1] = d1p[1];
+    fa.fail = fail;
+    fa.bits_out = l.bits_out;
+    fa.iters_out = l.iters_out;
+    fa.conv_out = l.conv_out;
+    fa.llr_out = l.llr_out;
+    fa.tot_frame = L.tot_frame;
+    fa.d1_frame = L.d1bits_frame;
+    fa.d1post_frame = L.d1post_frame;
+    fa.F = F;
+    fa.T = T;
+    finalize<<<dim3(tiles(c.n), F), dim3(kBlock), 0, st>>>(c, fa);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr) {
+    WorkLayout L{};
+    const size_t Z = (size_t)c.Z;
+    L.msg_frame = (size_t)c.NS * Z;
+    L.tot_frame = (size_t)c.NC * Z;
+    L.d1bits_frame = (size_t)c.ND1 * c.W;
+    L.synbits_frame = (size_t)c.mb * c.W;
+    L.d1post_frame = (size_t)c.ND1 * Z;
+    size_t off = 0;
+    L.msg = off;
+    off = align256(off + (size_t)F * L.msg_frame * (fp16 ? 2 : 4));
+    L.tot = off;
+    off = align256(off + (size_t)F * L.tot_frame * 4);
+    L.d1bits = off;
+    off = align256(off + 2 * (size_t)F * L.d1bits_frame * 8);
+    L.synbits = off;
+    off = align256(off + (size_t)F * L.synbits_frame * 8);
+    L.fail = off;
+    off = align256(off + (size_t)(T + 1) * F * 4);
+    L.d1post = off;
+    if (want_llr) off = align256(off + 2 * (size_t)F * L.d1post_frame * 4);
+    L.total = off;
+    return L;
+}
+
+hipError_t enqueue_decode(const DecodeLaunch &l) {
+    const WorkLayout L = work_layout(l.c, l.F, l.T, l.fp16 != 0, l.llr_out != nullptr);
+    return l.fp16 ? enqueue_typed<_Float16>(l, L) : enqueue_typed<float>(l, L);
+}
+
+hipError_t enqueue_syndrome(const CodeDev &c, int F, const uint8_t *bits, uint8_t *syn,
+                            hipStream_t stream) {
+    syndrome_kernel<<<dim3(tiles(c.Z), c.mb, F), dim3(kBlock), 0, stream>>>(c, bits, syn);
+    return hipGetLastError();
+}
+
+}  // namespace ldpc

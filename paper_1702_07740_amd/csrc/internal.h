@@ -1,0 +1,80 @@
+// Internal declarations shared by the decoder kernels (decoder.hip) and the
+// C-ABI layer (api.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ldpc {
+
+// Kinds of a non-zero base block, decided by the degree of its base column.
+//  STATE: the column has degree >= 2, so the block's Z check-to-variable
+//         messages are kept between iterations (the "state" edges).
+//  DEG1:  the column has degree 1.  Its variable-to-check message is the
+//         constant channel LLR (no other check feeds it), so nothing is stored;
+//         the posterior is Q + m and is formed only for decisions (the long
+//         diagonal of degree-1 parity bits, Sec. III-C).
+enum : int32_t { KIND_STATE = 0, KIND_DEG1 = 1 };
+enum : int32_t { COL_CORE = 0, COL_DEG1 = 1, COL_DEG0 = 2 };
+
+// Device view of a code: sizes plus pointers into small device tables.  Passed
+// by value as a kernel argument; every table index below is uniform across a
+// workgroup, so the loads are scalar.
+struct CodeDev {
+    int32_t Z, mb, nb, n, m;
+    int32_t NS;   // state blocks (messages per frame = NS * Z)
+    int32_t NC;   // core columns (degree >= 2)
+    int32_t ND1;  // degree-1 columns (= degree-1 blocks)
+    int32_t W;    // 64-bit words per Z bits
+    // per base row r: blocks row_first[r] .. row_first[r] + row_deg[r] - 1,
+    // in increasing column order
+    const int32_t *row_first, *row_deg;
+    // per block: shift, kind, ref (state index or degree-1 index), column,
+    // core index of the column (state blocks only, else -1)
+    const int32_t *blk_shift, *blk_kind, *blk_ref, *blk_col, *blk_core;
+    // per core column k: its base column, and its state blocks
+    // core_state[core_first[k] + i], core_shift[...], i < core_deg[k], in
+    // increasing row order
+    const int32_t *core_col, *core_first, *core_deg, *core_state, *core_shift;
+    // per base column: kind and index within its kind
+    const int32_t *col_kind, *col_ref;
+    // per degree-1 column: shift of its only block
+    const int32_t *d1_shift;
+};
+
+// Byte offsets of the decode workspace for F frames and T iterations.
+struct WorkLayout {
+    size_t msg, tot, d1bits, synbits, fail, d1post, total;
+    size_t msg_frame;      // elements per frame
+    size_t tot_frame;      // floats per frame
+    size_t d1bits_frame;   // words per frame
+    size_t synbits_frame;  // words per frame
+    size_t d1post_frame;   // floats per frame
+};
+
+WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr);
+
+struct DecodeLaunch {
+    CodeDev c;
+    int F, T;
+    int early_stop, check_from, fp16;
+    const float *llr;
+    const uint8_t *syndrome;
+    uint8_t *bits_out;
+    int32_t *iters_out;
+    uint8_t *conv_out;
+    float *llr_out;
+    char *ws;
+    hipEvent_t *events;    // optional: 2T + 1 caller events around the iteration kernels
+    hipStream_t stream;
+};
+
+// Enqueue the whole decode on l.stream.  Returns hipSuccess or the first
+// launch error.
+hipError_t enqueue_decode(const DecodeLaunch &l);
+hipError_t enqueue_syndrome(const CodeDev &c, int F, const uint8_t *bits, uint8_t *syn,
+                            hipStream_t stream);
+
+}  // namespace ldpc

@@ -1,0 +1,218 @@
+"""Thin ctypes binding of libldpc.so (C ABI in include/ldpc.h).
+
+Argument marshalling only: every step of decoding runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors) and streams.  If the
+library is not built, loading raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldpc.so")
+
+LDPC_OK = 0
+LDPC_EINVAL = -1
+LDPC_ENOMEM = -2
+LDPC_EDEVICE = -3
+LDPC_EUNSUPPORTED = -4
+LDPC_EWORKSPACE = -5
+MAX_ROW_DEGREE = 16
+
+EXPORTS = (
+    "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_info", "ldpc_decode_opts_init",
+    "ldpc_workspace_bytes", "ldpc_decode_batch", "ldpc_syndrome", "ldpc_status_string",
+    "ldpc_last_error",
+)
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({_status_text(status)}): {detail}")
+        self.status = status
+
+
+class CodeInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("m", ctypes.c_int32), ("Z", ctypes.c_int32),
+        ("mb", ctypes.c_int32), ("nb", ctypes.c_int32), ("blocks", ctypes.c_int32),
+        ("edges", ctypes.c_int64), ("state_edges", ctypes.c_int64),
+        ("core_cols", ctypes.c_int32), ("deg1_cols", ctypes.c_int32),
+        ("deg0_cols", ctypes.c_int32), ("max_row_degree", ctypes.c_int32),
+    ]
+
+
+class DecodeOpts(ctypes.Structure):
+    _fields_ = [
+        ("early_stop", ctypes.c_int32), ("check_from_iter", ctypes.c_int32),
+        ("msg_fp16", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("llr_out", ctypes.c_void_p),
+        ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
+    ]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libldpc.so once; raise if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(
+                f"{path} is missing: build the HIP decoder first (__graft_entry__.build())")
+        lib = ctypes.CDLL(path)
+        P, I32 = ctypes.c_void_p, ctypes.c_int32
+        lib.ldpc_code_create.restype = ctypes.c_int
+        lib.ldpc_code_create.argtypes = [I32, I32, P, I32, ctypes.POINTER(P)]
+        lib.ldpc_code_destroy.restype = None
+        lib.ldpc_code_destroy.argtypes = [P]
+        lib.ldpc_code_info.restype = ctypes.c_int
+        lib.ldpc_code_info.argtypes = [P, ctypes.POINTER(CodeInfo)]
+        lib.ldpc_decode_opts_init.restype = None
+        lib.ldpc_decode_opts_init.argtypes = [ctypes.POINTER(DecodeOpts)]
+        lib.ldpc_workspace_bytes.restype = ctypes.c_size_t
+        lib.ldpc_workspace_bytes.argtypes = [P, I32, I32, ctypes.POINTER(DecodeOpts)]
+        lib.ldpc_decode_batch.restype = ctypes.c_int
+        lib.ldpc_decode_batch.argtypes = [P, I32, P, P, I32, P, P, P,
+                                          ctypes.POINTER(DecodeOpts), P, ctypes.c_size_t, P]
+        lib.ldpc_syndrome.restype = ctypes.c_int
+        lib.ldpc_syndrome.argtypes = [P, I32, P, P, P]
+        lib.ldpc_status_string.restype = ctypes.c_char_p
+        lib.ldpc_status_string.argtypes = [ctypes.c_int]
+        lib.ldpc_last_error.restype = ctypes.c_char_p
+        lib.ldpc_last_error.argtypes = []
+        _lib = lib
+        return lib
+
+
+def _status_text(status: int) -> str:
+    return load().ldpc_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != LDPC_OK:
+        raise LdpcError(status, where, load().ldpc_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_opts(early_stop=True, check_from_iter=0, msg_fp16=False, llr_out_ptr=None,
+              timing_events=None) -> DecodeOpts:
+    o = DecodeOpts()
+    load().ldpc_decode_opts_init(ctypes.byref(o))
+    o.early_stop = int(bool(early_stop))
+    o.check_from_iter = int(check_from_iter)
+    o.msg_fp16 = int(bool(msg_fp16))
+    o.llr_out = llr_out_ptr
+    if timing_events is not None:
+        o.timing_events = timing_events
+        o.n_timing_events = len(timing_events)
+    return o
+
+
+class Code:
+    """A QC code on the current HIP device (ldpc_code_create)."""
+
+    def __init__(self, base, Z: int):
+        lib = load()
+        b = np.ascontiguousarray(np.asarray(base), dtype=np.int32)
+        if b.ndim != 2:
+            raise ValueError("base must be a 2-D matrix")
+        self.base = b
+        h = ctypes.c_void_p()
+        st = lib.ldpc_code_create(b.shape[0], b.shape[1], b.ctypes.data_as(ctypes.c_void_p),
+                                  int(Z), ctypes.byref(h))
+        _check(st, "ldpc_code_create")
+        self._h = h
+        info = CodeInfo()
+        _check(lib.ldpc_code_info(h, ctypes.byref(info)), "ldpc_code_info")
+        self.info = {k: getattr(info, k) for k, _ in CodeInfo._fields_}
+        self.n, self.m, self.Z = info.n, info.m, info.Z
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ldpc_code_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self, F: int, max_iters: int, msg_fp16=False, want_llr=False) -> int:
+        o = make_opts(msg_fp16=msg_fp16, llr_out_ptr=1 if want_llr else None)
+        return int(load().ldpc_workspace_bytes(self._h, int(F), int(max_iters), ctypes.byref(o)))
+
+    def alloc_workspace(self, F, max_iters, msg_fp16=False, want_llr=False, device=None):
+        import torch
+        nbytes = self.workspace_bytes(F, max_iters, msg_fp16, want_llr)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+        off = (-ws.data_ptr()) % 256
+        return ws[off:off + nbytes]
+
+    def decode(self, llr, syndrome, max_iters: int, early_stop=True, check_from_iter=0,
+               msg_fp16=False, want_llr=False, workspace=None, out=None, stream=None,
+               timing_events=None):
+        """Decode frames llr [F][n] float32 / syndrome [F][m] uint8 (CUDA tensors).
+
+        Returns (bits uint8 [F][n], iters int32 [F], converged uint8 [F], L or None),
+        all CUDA tensors, valid once ``stream`` (default: current) is synchronised.
+        """
+        import torch
+        if llr.dtype != torch.float32 or syndrome.dtype != torch.uint8:
+            raise TypeError("llr must be float32 and syndrome uint8")
+        if not (llr.is_cuda and syndrome.is_cuda):
+            raise TypeError("llr and syndrome must be device tensors")
+        if llr.dim() != 2 or llr.shape[1] != self.n or syndrome.shape != (llr.shape[0], self.m):
+            raise ValueError("expected llr [F][n] and syndrome [F][m]")
+        llr = llr.contiguous()
+        syndrome = syndrome.contiguous()
+        F = llr.shape[0]
+        dev = llr.device
+        if out is None:
+            bits = torch.empty((F, self.n), dtype=torch.uint8, device=dev)
+            iters = torch.empty(F, dtype=torch.int32, device=dev)
+            conv = torch.empty(F, dtype=torch.uint8, device=dev)
+            L = torch.empty((F, self.n), dtype=torch.float32, device=dev) if want_llr else None
+        else:
+            bits, iters, conv, L = out
+        if workspace is None:
+            workspace = self.alloc_workspace(F, max_iters, msg_fp16, want_llr, dev)
+        opts = make_opts(early_stop, check_from_iter, msg_fp16,
+                         L.data_ptr() if L is not None else None, timing_events)
+        st = load().ldpc_decode_batch(
+            self._h, F, llr.data_ptr(), syndrome.data_ptr(), int(max_iters),
+            bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ctypes.byref(opts),
+            workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
+        _check(st, "ldpc_decode_batch")
+        return bits, iters, conv, L
+
+    def syndrome(self, bits, stream=None):
+        """H x mod 2 for uint8 words [F][n] (CUDA tensor) -> uint8 [F][m]."""
+        import torch
+        if bits.dtype != torch.uint8 or not bits.is_cuda or bits.dim() != 2 or bits.shape[1] != self.n:
+            raise ValueError("expected a uint8 device tensor [F][n]")
+        bits = bits.contiguous()
+        syn = torch.empty((bits.shape[0], self.m), dtype=torch.uint8, device=bits.device)
+        st = load().ldpc_syndrome(self._h, bits.shape[0], bits.data_ptr(), syn.data_ptr(),
+                                  _stream_handle(stream))
+        _check(st, "ldpc_syndrome")
+        return syn

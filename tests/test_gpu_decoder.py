@@ -1,0 +1,342 @@
+"""Parity of the HIP decoder (through the C ABI) against the FP64 oracle.
+
+Every case prints its name, seed and shape before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+from paper_1702_07740_amd import synth
+from tests.parity import LLR_RTOL, check_decode_parity, llr_close
+from tests.qc_dense import random_tree_base
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ldpc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_07740_amd import ldpc as mod
+    mod.load()
+    return mod
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _gpu_decode(gcode, Q, s, T, **kw):
+    bits, it, conv, L = gcode.decode(_dev(Q), _dev(s), T, **kw)
+    torch.cuda.synchronize()
+    return (bits.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy(),
+            None if L is None else L.cpu().numpy())
+
+
+def _codes(ldpc, oracle_mod, base, Z):
+    return ldpc.Code(base, Z), oracle_mod.OracleCode(base, Z)
+
+
+# ------------------------------------------------------------ syndromes
+@pytest.mark.parametrize("kind,Z", [("template", 64), ("template", 67), ("template", 1),
+                                    ("random", 13), ("random", 300), ("template", 6667)])
+def test_syndrome_bit_exact(ldpc, oracle_mod, kind, Z):
+    rng = np.random.default_rng(Z)
+    if kind == "template":
+        base = synth.template_base(144, Z, seed=5)
+    else:
+        base = rng.integers(-1, Z, size=(7, 11)).astype(np.int32)
+        base[:, 3] = -1            # a degree-0 column
+        base[:, 4] = -1
+        base[2, 4] = 5 % Z         # a degree-1 column
+        base[np.all(base < 0, axis=1), 0] = 0
+    _say("syndrome", kind, "Z", Z, "base", base.shape)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x = rng.integers(0, 2, size=(3, o.n)).astype(np.uint8)
+    got = g.syndrome(_dev(x)).cpu().numpy()
+    assert np.array_equal(got, o.syndrome(x))
+
+
+# ------------------------------------------------- per-iteration posteriors
+@pytest.mark.parametrize("snr", [-15.4, -13.0])
+@pytest.mark.parametrize("T", [1, 2, 5, 10])
+def test_posterior_llr_per_iteration(ldpc, oracle_mod, snr, T):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x, Q = synth.biawgn_frames(o.n, 4, snr, seed=40 + T)
+    s = o.syndrome(x)
+    _say("posterior", "snr", snr, "T", T, "n", o.n)
+    bits, it, conv, L = _gpu_decode(g, Q, s, T, early_stop=False, want_llr=True)
+    b_r, L_r, it_r, c_r = o.decode(Q, s, T, early_stop=False)
+    ok, worst, nbad = llr_close(L, L_r)
+    assert ok, f"worst error/bound {worst:.3g}, {nbad} entries over"
+    assert np.all(it == T) and np.all(it_r == T)
+    margin = 2 * LLR_RTOL * np.maximum(np.abs(L_r), 1.0)
+    sure = np.abs(L_r) > margin
+    assert np.array_equal(bits[sure], b_r[sure])
+    assert np.array_equal(bits, (L < 0).astype(np.uint8))
+
+
+# --------------------------------------------------- early-stop decoding
+@pytest.mark.parametrize("snr,F,seed", [(-15.4, 16, 1), (-14.0, 16, 2), (-13.0, 16, 3),
+                                        (-12.0, 8, 4)])
+def test_decode_parity_small_template(ldpc, oracle_mod, snr, F, seed):
+    """The n = 9600 template (Z = 64), 16 frames, max 100 iterations, early stop."""
+    Z, T = 64, 100
+    base = synth.template_base(144, Z, seed=1)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x, Q = synth.biawgn_frames(o.n, F, snr, seed=seed)
+    s = o.syndrome(x)
+    _say("decode", "snr", snr, "F", F, "n", o.n)
+    bits, it, conv, L = _gpu_decode(g, Q, s, T, want_llr=True)
+    ref = o.decode(Q, s, T, threads=8)
+    summ = check_decode_parity(o, Q, s, bits, it, conv, ref, T)
+    print("summary", summ, flush=True)
+    assert summ["gpu_only"] + summ["ref_only"] <= max(1, F // 8)
+    both = np.logical_and(conv.astype(bool), ref[3])
+    for f in np.nonzero(both)[0]:
+        if it[f] == ref[2][f]:
+            ok, worst, _ = llr_close(L[f], ref[1][f])
+            assert ok, f"frame {f}: posterior worst {worst:.3g}"
+
+
+def test_noiseless_frames_stop_at_zero(ldpc, oracle_mod):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x = synth.random_bits(o.n, 5, seed=9)
+    s = o.syndrome(x)
+    Q = synth.noiseless_llr(x, 4.0)
+    _say("noiseless", "n", o.n)
+    bits, it, conv, L = _gpu_decode(g, Q, s, 30, want_llr=True)
+    assert np.all(it == 0) and np.all(conv == 1)
+    assert np.array_equal(bits, x)
+    assert np.array_equal(L, Q)
+
+
+@pytest.mark.parametrize("which", ["core", "deg1"])
+def test_one_weak_wrong_bit(ldpc, oracle_mod, which):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x = synth.random_bits(o.n, 1, seed=12)
+    s = o.syndrome(x)
+    Q = synth.noiseless_llr(x, 5.0)
+    v = 2 * Z + 3 if which == "core" else 40 * Z + 5
+    Q[0, v] = -0.1 * (1 - 2.0 * x[0, v])
+    _say("weak bit", which)
+    bits, it, conv, _ = _gpu_decode(g, Q, s, 50)
+    assert it[0] == 1 and conv[0] == 1 and np.array_equal(bits[0], x[0])
+
+
+def test_tree_forest_matches_oracle(ldpc, oracle_mod):
+    """A Z-lift of a cycle-free base graph is a forest: BP is exact MAP there."""
+    rng = np.random.default_rng(77)
+    Z = 64
+    base = random_tree_base(rng, 14, 5, Z)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    Q = (rng.uniform(0.2, 2.5, size=(2, o.n)) * rng.choice([-1.0, 1.0], size=(2, o.n))).astype(np.float32)
+    s = o.syndrome(rng.integers(0, 2, size=(2, o.n)).astype(np.uint8))
+    _say("tree forest", base.shape)
+    T = 25
+    bits, it, conv, L = _gpu_decode(g, Q, s, T, early_stop=False, want_llr=True)
+    _, L_r, _, _ = o.decode(Q, s, T, early_stop=False)
+    ok, worst, _ = llr_close(L, L_r)
+    assert ok, worst
+
+
+def test_coset_equivariance_bitwise(ldpc, oracle_mod):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    rng = np.random.default_rng(5)
+    x, Q = synth.biawgn_frames(o.n, 4, -13.0, seed=51)
+    s = o.syndrome(x)
+    a = rng.integers(0, 2, size=x.shape).astype(np.uint8)
+    Q2 = np.where(a == 1, -Q, Q).astype(np.float32)
+    s2 = s ^ o.syndrome(a)
+    _say("coset")
+    b1, i1, c1, L1 = _gpu_decode(g, Q, s, 60, want_llr=True)
+    b2, i2, c2, L2 = _gpu_decode(g, Q2, s2, 60, want_llr=True)
+    assert np.array_equal(b1 ^ a, b2)
+    assert np.array_equal(i1, i2) and np.array_equal(c1, c2)
+    assert np.array_equal(np.where(a == 1, -L1, L1), L2)
+
+
+def test_deterministic_and_batch_independent(ldpc, oracle_mod):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    x, Q = synth.biawgn_frames(o.n, 6, -13.5, seed=61)
+    s = o.syndrome(x)
+    _say("determinism")
+    r1 = _gpu_decode(g, Q, s, 80, want_llr=True)
+    r2 = _gpu_decode(g, Q, s, 80, want_llr=True)
+    for u, v in zip(r1, r2):
+        assert np.array_equal(u, v)
+    for f in (0, 3, 5):
+        alone = _gpu_decode(g, Q[f:f + 1], s[f:f + 1], 80, want_llr=True)
+        for u, v in zip(alone, r1):
+            assert np.array_equal(u[0], v[f])
+
+
+# ------------------------------------------------------------ edge cases
+def test_zero_iterations(ldpc, oracle_mod):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x, Q = synth.biawgn_frames(o.n, 3, -10.0, seed=3)
+    s = o.syndrome(x)
+    Q[1] = synth.noiseless_llr(x[1], 2.0)
+    _say("T=0")
+    bits, it, conv, L = _gpu_decode(g, Q, s, 0, want_llr=True)
+    b_r, L_r, it_r, c_r = o.decode(Q, s, 0)
+    assert np.array_equal(bits, b_r) and np.all(it == 0)
+    assert np.array_equal(conv.astype(bool), c_r) and conv[1] == 1
+    assert np.array_equal(L, Q)
+
+
+def test_check_from_and_no_early_stop(ldpc, oracle_mod):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x = synth.random_bits(o.n, 2, seed=13)
+    s = o.syndrome(x)
+    Q = synth.noiseless_llr(x, 3.0)
+    _say("check_from")
+    _, it, conv, _ = _gpu_decode(g, Q, s, 20, check_from_iter=4)
+    assert np.all(it == 4) and np.all(conv == 1)
+    _, it, conv, _ = _gpu_decode(g, Q, s, 7, early_stop=False)
+    assert np.all(it == 7) and np.all(conv == 1)
+
+
+@pytest.mark.parametrize("Z", [1, 3, 63, 65, 257, 1000])
+def test_ragged_lifting_sizes(ldpc, oracle_mod, Z):
+    base = synth.template_base(24, Z, seed=2)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x, Q = synth.biawgn_frames(o.n, 3, -4.0, seed=Z)
+    s = o.syndrome(x)
+    _say("ragged Z", Z, "n", o.n)
+    for T in (3,):
+        bits, it, conv, L = _gpu_decode(g, Q, s, T, early_stop=False, want_llr=True)
+        _, L_r, _, _ = o.decode(Q, s, T, early_stop=False)
+        ok, worst, _ = llr_close(L, L_r)
+        assert ok, worst
+    bits, it, conv, L = _gpu_decode(g, Q, s, 50)
+    check_decode_parity(o, Q, s, bits, it, conv, o.decode(Q, s, 50), 50)
+
+
+def test_general_code_with_degree_0_and_degree_1_rows(ldpc, oracle_mod):
+    """Columns of degree 0, 1 and >= 2; check rows of degree 1, 2, 7 and 16."""
+    rng = np.random.default_rng(8)
+    Z = 37
+    mb, nb = 6, 20
+    base = np.full((mb, nb), -1, dtype=np.int32)
+    base[0, :16] = rng.integers(0, Z, 16)          # degree-16 row
+    base[1, 2] = 4                                 # degree-1 row
+    base[2, [0, 17]] = [3, 9]                      # degree-2 row, column 17 has degree 1
+    base[3, [1, 3, 5, 7, 9, 11, 18]] = rng.integers(0, Z, 7)
+    base[4, [0, 2, 4]] = rng.integers(0, Z, 3)
+    base[5, [6, 8, 10]] = rng.integers(0, Z, 3)
+    # column 19 stays empty (degree 0)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    info = g.info
+    assert info["deg0_cols"] == 1 and info["max_row_degree"] == 16
+    x, Q = synth.biawgn_frames(o.n, 4, 0.0, seed=8)
+    s = o.syndrome(x)
+    _say("general code", base.shape, Z)
+    for T in (1, 4):
+        bits, it, conv, L = _gpu_decode(g, Q, s, T, early_stop=False, want_llr=True)
+        _, L_r, _, _ = o.decode(Q, s, T, early_stop=False)
+        ok, worst, _ = llr_close(L, L_r)
+        assert ok, worst
+    bits, it, conv, L = _gpu_decode(g, Q, s, 40)
+    check_decode_parity(o, Q, s, bits, it, conv, o.decode(Q, s, 40), 40)
+
+
+def test_invalid_arguments(ldpc):
+    Z = 16
+    base = synth.template_base(24, Z, seed=2)
+    g = ldpc.Code(base, Z)
+    lib = ldpc.load()
+    Q = torch.zeros((2, g.n), dtype=torch.float32, device="cuda")
+    s = torch.zeros((2, g.m), dtype=torch.uint8, device="cuda")
+    bits = torch.empty((2, g.n), dtype=torch.uint8, device="cuda")
+    it = torch.empty(2, dtype=torch.int32, device="cuda")
+    cv = torch.empty(2, dtype=torch.uint8, device="cuda")
+    ws = g.alloc_workspace(2, 10)
+    o = ldpc.make_opts()
+    import ctypes
+
+    def call(F, T, wsp, wsn, q=Q.data_ptr()):
+        return lib.ldpc_decode_batch(g.handle, F, q, s.data_ptr(), T, bits.data_ptr(),
+                                     it.data_ptr(), cv.data_ptr(), ctypes.byref(o), wsp, wsn, None)
+
+    _say("invalid args")
+    assert call(0, 10, ws.data_ptr(), ws.numel()) == ldpc.LDPC_EINVAL
+    assert call(2, -1, ws.data_ptr(), ws.numel()) == ldpc.LDPC_EINVAL
+    assert call(2, 10, ws.data_ptr(), ws.numel(), q=None) == ldpc.LDPC_EINVAL
+    assert call(2, 10, ws.data_ptr(), ws.numel() - 1) == ldpc.LDPC_EWORKSPACE
+    assert call(2, 10, None, ws.numel()) == ldpc.LDPC_EWORKSPACE
+    assert call(2, 10, ws.data_ptr(), ws.numel()) == ldpc.LDPC_OK
+    torch.cuda.synchronize()
+    assert np.all(it.cpu().numpy() <= 10)
+    with pytest.raises(ldpc.LdpcError):
+        ldpc.Code(np.array([[0, Z]], dtype=np.int32), Z)
+    with pytest.raises(ldpc.LdpcError):
+        ldpc.Code(np.zeros((1, 17), dtype=np.int32), Z)   # row degree 17 > 16
+
+
+# ------------------------------------------- full size (n = 1,000,050)
+@pytest.fixture(scope="module")
+def full_code(ldpc, oracle_mod):
+    Z = 6667
+    base = synth.template_base(144, Z, seed=1)
+    return ldpc.Code(base, Z), oracle_mod.OracleCode(base, Z)
+
+
+def test_full_size_posterior_after_two_iterations(full_code):
+    g, o = full_code
+    x, Q = synth.biawgn_frames(o.n, 2, -15.4, seed=1)
+    s = o.syndrome(x)
+    _say("full size posterior", o.n)
+    bits, it, conv, L = _gpu_decode(g, Q, s, 2, early_stop=False, want_llr=True)
+    _, L_r, _, _ = o.decode(Q[:1], s[:1], 2, early_stop=False)
+    ok, worst, _ = llr_close(L[0], L_r[0])
+    assert ok, worst
+
+
+def test_full_size_bench_configuration_properties(full_code):
+    """The benchmark's decode (8 frames, SNR -15.4 dB, 100 iterations, early stop):
+    every frame's flag equals H x = s recomputed on the CPU, and counts are in range."""
+    g, o = full_code
+    F, T = 8, 100
+    x, Q = synth.biawgn_frames(o.n, F, -15.4, seed=1)
+    s = o.syndrome(x)
+    _say("full size bench config", F, T)
+    bits, it, conv, _ = _gpu_decode(g, Q, s, T)
+    syn = o.syndrome(bits)
+    for f in range(F):
+        assert bool(conv[f]) == np.array_equal(syn[f], s[f])
+        assert 0 <= it[f] <= T
+        assert conv[f] or it[f] == T
+
+
+def test_full_size_converged_frames_match_oracle(full_code):
+    g, o = full_code
+    F, T = 2, 100
+    x, Q = synth.biawgn_frames(o.n, F, -13.8, seed=2)
+    s = o.syndrome(x)
+    _say("full size converged parity", F, T)
+    bits, it, conv, _ = _gpu_decode(g, Q, s, T)
+    ref = o.decode(Q, s, T, threads=2)
+    summ = check_decode_parity(o, Q, s, bits, it, conv, ref, T)
+    print("summary", summ, it, ref[2], flush=True)
+    assert summ["both"] >= 1
