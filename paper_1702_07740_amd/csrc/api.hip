@@ -177,6 +177,13 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     const size_t o_cc = put(core_col), o_cf = put(core_first), o_cd = put(core_deg),
                  o_cs = put(core_state), o_csh = put(core_shift);
     const size_t o_colk = put(col_kind), o_colr = put(col_ref), o_d1s = put(d1_shift);
+    std::vector<int32_t> row_list;
+    for (int r = 0; r < mb; ++r)
+        if (row_deg[r] <= ldpc::kSmallRowDegree) row_list.push_back(r);
+    const int n_small = (int)row_list.size();
+    for (int r = 0; r < mb; ++r)
+        if (row_deg[r] > ldpc::kSmallRowDegree) row_list.push_back(r);
+    const size_t o_rl = put(row_list);
 
     ldpc_code *code = new (std::nothrow) ldpc_code();
     if (!code) return fail_with(LDPC_ENOMEM, "host allocation failed");
@@ -210,6 +217,9 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.W = (Z + 63) / 64;
     d.row_first = T + o_row_first;
     d.row_deg = T + o_row_deg;
+    d.row_list = T + o_rl;
+    d.n_small = n_small;
+    d.n_large = mb - n_small;
     d.blk_shift = T + o_bs;
     d.blk_kind = T + o_bk;
     d.blk_ref = T + o_br;

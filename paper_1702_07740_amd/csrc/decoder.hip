@@ -36,11 +36,41 @@ constexpr int kBlock = 256;  // threads per workgroup: 4 wave64s
 constexpr float kPhiLo = 1e-7f;
 constexpr float kPhiHi = 30.0f;
 
-// Phi(x) = -ln tanh(x/2) on the clamped argument, evaluated as
-// log1p(2 / expm1(x)) so that large x keeps full relative precision.
+// Phi(x) = -ln tanh(x/2) on the clamped argument [1e-7, 30], from the
+// hardware base-2 exponential, logarithm and reciprocal:
+//   with t = e^{-x}, Phi(x) = ln((1 + t) / (1 - t)) = 2 atanh(t).
+//   x >= 1.5 (t <= 0.223): the odd series 2t (1 + t^2/3 + ... + t^10/11),
+//            truncation below 1e-8 relative, no cancellation for large x;
+//   x <  1.5: ln((2 - d) / d) with d = 1 - t, where d comes from the Taylor
+//            series of 1 - e^{-x} when x < 0.1 so that small x keeps its
+//            relative precision.
+// Relative error below 2e-6 over the whole range (below 3e-7 for x < 25).
 __device__ __forceinline__ float phi_f32(float x) {
+    constexpr float kLog2e = 1.4426950408889634f;
+    constexpr float kLn2 = 0.6931471805599453f;
     x = fminf(fmaxf(x, kPhiLo), kPhiHi);
-    return log1pf(2.0f / expm1f(x));
+    const float t = __builtin_amdgcn_exp2f(-x * kLog2e);
+    if (x >= 1.5f) {
+        const float t2 = t * t;
+        float p = fmaf(t2, 1.0f / 11.0f, 1.0f / 9.0f);
+        p = fmaf(t2, p, 1.0f / 7.0f);
+        p = fmaf(t2, p, 1.0f / 5.0f);
+        p = fmaf(t2, p, 1.0f / 3.0f);
+        p = fmaf(t2, p, 1.0f);
+        return 2.0f * t * p;
+    }
+    float d;
+    if (x < 0.1f) {
+        float p = fmaf(x, 1.0f / 120.0f, -1.0f / 24.0f);
+        p = fmaf(x, p, 1.0f / 6.0f);
+        p = fmaf(x, p, -0.5f);
+        p = fmaf(x, p, 1.0f);
+        d = x * p;
+    } else {
+        d = 1.0f - t;
+    }
+    const float q = (2.0f - d) * __builtin_amdgcn_rcpf(d);
+    return __builtin_amdgcn_logf(q) * kLn2;
 }
 
 template <typename Msg> __device__ __forceinline__ float msg_load(const Msg *p);
@@ -74,123 +104,199 @@ struct CnArgs {
     int skip_after;            // frame inactive if fail[skip_after][f] == 0 (-1: never)
 };
 
-// One check (r, a) of one frame, row degree D.  `valid` is false for the
-// padding lanes a >= Z of the last tile; they take part in the wave ballots
-// with zero bits and touch no memory.
-template <int D, typename Msg>
-__device__ __forceinline__ void check_update(const CodeDev &c, const CnArgs &A, int f, int r,
-                                             int a, bool valid) {
-    const int Z = c.Z;
-    const int b0 = c.row_first[r];
-    const float *llr = A.llr + (size_t)f * c.n;
-    const float *tot = A.tot + (size_t)f * A.tot_frame;
-    Msg *msg = reinterpret_cast<Msg *>(A.msg) + (size_t)f * A.msg_frame;
-    const int w = a >> 6;
-    const int bit = a & 63;
+// Per-row block data, uniform across a workgroup (scalar registers).
+template <int D>
+struct RowInfo {
+    int shift[D];        // circulant shift of each block
+    int ref[D];          // state index (stored blocks) or degree-1 index
+    int src[D];          // core index (stored blocks) or base column (degree-1)
+    unsigned state_mask; // bit k set: block k keeps stored messages
+};
 
-    float x[D];         // variable-to-check inputs L_vc of iteration t-1
-    int vpar = 0;       // parity of the iteration t-1 decisions on this check
+template <int D>
+__device__ __forceinline__ RowInfo<D> load_row(const CodeDev &c, int r) {
+    RowInfo<D> ri;
+    const int b0 = c.row_first[r];
+    ri.state_mask = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const int b = b0 + k;
-        const int s = c.blk_shift[b];
-        int j = a + s;
-        j -= (j >= Z) ? Z : 0;
-        float xv = 1.0f;
-        int dec = 0;
-        if (c.blk_kind[b] == KIND_STATE) {
-            if (valid) {
-                const float lt = tot[(size_t)c.blk_core[b] * Z + j];
-                dec = lt < 0.0f;
-                float mo = 0.0f;
-                if (A.update && !A.first) mo = msg_load<Msg>(msg + (size_t)c.blk_ref[b] * Z + a);
-                xv = lt - mo;
-            }
-        } else {
-            if (valid) {
-                xv = llr[(size_t)c.blk_col[b] * Z + j];
+        const bool st = c.blk_kind[b] == KIND_STATE;
+        ri.shift[k] = c.blk_shift[b];
+        ri.ref[k] = c.blk_ref[b];
+        ri.src[k] = st ? c.blk_core[b] : c.blk_col[b];
+        ri.state_mask |= (unsigned)st << k;
+    }
+    return ri;
+}
+
+// Checks per thread: a thread handles checks a, a + 256, a + 512, a + 768 of
+// one row, so the row's table reads are paid once and every thread has its
+// loads for several checks in flight together.
+constexpr int kChecksPerThread = 4;
+// how many of those are processed at once (bounded by registers for large D)
+template <int D> struct ChunkOf { static constexpr int value = D <= 4 ? 4 : (D <= 8 ? 2 : 1); };
+
+// K checks (r, a_first + q*256), q < K, of one frame, row degree D.  Padding
+// lanes (a >= Z) take part in the wave ballots with zero bits and touch no
+// memory.  Returns 1 if one of this thread's checks fails the parity check of
+// the voted iteration.
+template <int D, int K, typename Msg>
+__device__ __forceinline__ int check_chunk(const CodeDev &c, const CnArgs &A, const RowInfo<D> &ri,
+                                           int f, int r, int a_first) {
+    const int Z = c.Z;
+    const float *llr = A.llr + (size_t)f * c.n;
+    const float *tot = A.tot + (size_t)f * A.tot_frame;
+    Msg *msg = reinterpret_cast<Msg *>(A.msg) + (size_t)f * A.msg_frame;
+    const uint64_t *syn = A.synbits + (size_t)f * A.syn_frame + (size_t)r * c.W;
+    const bool read_old = A.update && !A.first;
+
+    float x[K][D];  // variable-to-check inputs L_vc of iteration t-1
+    int vpar[K];    // parity of the voted decisions on each check, with s_c
+    int sb[K];      // syndrome bits
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const int a = a_first + q * kBlock;
+        const bool valid = a < Z;
+        const int w = a >> 6, bit = a & 63;
+        sb[q] = valid ? (int)((syn[w] >> bit) & 1ull) : 0;
+        int par = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            int j = a + ri.shift[k];
+            j -= (j >= Z) ? Z : 0;
+            float xv = 1.0f;
+            int dec = 0;
+            if ((ri.state_mask >> k) & 1u) {
+                if (valid) {
+                    const float lt = tot[(size_t)ri.src[k] * Z + j];
+                    dec = lt < 0.0f;
+                    const float mo = read_old ? msg_load<Msg>(msg + (size_t)ri.ref[k] * Z + a) : 0.0f;
+                    xv = lt - mo;
+                }
+            } else if (valid) {
+                xv = llr[(size_t)ri.src[k] * Z + j];
                 if (A.vote) {
                     if (A.d1_from_llr) {
                         dec = xv < 0.0f;
                     } else {
                         const uint64_t wd =
-                            A.d1_prev[(size_t)f * A.d1_frame + (size_t)c.blk_ref[b] * c.W + w];
+                            A.d1_prev[(size_t)f * A.d1_frame + (size_t)ri.ref[k] * c.W + w];
                         dec = (int)((wd >> bit) & 1ull);
                     }
                 }
             }
+            x[q][k] = xv;
+            par ^= dec;
         }
-        x[k] = xv;
-        vpar ^= dec;
+        vpar[q] = valid ? (par ^ sb[q]) : 0;
     }
-
+    int bad = 0;
     if (A.vote) {
-        int sbit = 0;
-        if (valid) sbit = (int)((A.synbits[(size_t)f * A.syn_frame + (size_t)r * c.W + w] >> bit) & 1ull);
-        const unsigned long long bad = wave_ballot(valid && (vpar ^ sbit));
-        if (bad != 0ull && (threadIdx.x & 63) == 0)
-            __hip_atomic_store(A.fail + (size_t)(A.update ? A.t - 1 : A.t) * A.F + f, 1,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (!A.update) return;
-
-    // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums.
-    float ph[D];
-    int neg = 0;
-    int par = 0;
-    if (valid) par = (int)((A.synbits[(size_t)f * A.syn_frame + (size_t)r * c.W + w] >> bit) & 1ull);
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const int nk = x[k] < 0.0f;
-        neg |= nk << k;
-        par ^= nk;
-        ph[k] = phi_f32(fabsf(x[k]));
+        for (int q = 0; q < K; ++q) bad |= vpar[q];
     }
-    float pre[D];
-    pre[0] = 0.0f;
-#pragma unroll
-    for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + ph[k - 1];
-    float suf = 0.0f;
-    float out[D];
-#pragma unroll
-    for (int k = D - 1; k >= 0; --k) {
-        const float mag = phi_f32(pre[k] + suf);
-        suf += ph[k];
-        out[k] = ((par ^ (neg >> k)) & 1) ? -mag : mag;
-    }
+    if (!A.update) return bad;
 
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const int b = b0 + k;
-        if (c.blk_kind[b] == KIND_STATE) {
-            if (valid) msg_store<Msg>(msg + (size_t)c.blk_ref[b] * Z + a, out[k]);
-        } else {
-            const float lp = x[k] + out[k];  // posterior of the degree-1 variable
-            const unsigned long long bits = wave_ballot(valid && lp < 0.0f);
-            const int ref = c.blk_ref[b];
-            if ((threadIdx.x & 63) == 0 && a < Z)
-                A.d1_cur[(size_t)f * A.d1_frame + (size_t)ref * c.W + w] = bits;
-            if (A.d1post && valid) A.d1post[(size_t)f * A.d1post_frame + (size_t)ref * Z + a] = lp;
+    for (int q = 0; q < K; ++q) {
+        const int a = a_first + q * kBlock;
+        const bool valid = a < Z;
+        const int w = a >> 6;
+        // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
+        float ph[D];
+        int neg = 0, par = sb[q];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int nk = x[q][k] < 0.0f;
+            neg |= nk << k;
+            par ^= nk;
+            ph[k] = phi_f32(fabsf(x[q][k]));
+        }
+        float pre[D];
+        pre[0] = 0.0f;
+#pragma unroll
+        for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + ph[k - 1];
+        float suf = 0.0f;
+        float out[D];
+#pragma unroll
+        for (int k = D - 1; k >= 0; --k) {
+            const float mag = phi_f32(pre[k] + suf);
+            suf += ph[k];
+            out[k] = ((par ^ (neg >> k)) & 1) ? -mag : mag;
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if ((ri.state_mask >> k) & 1u) {
+                if (valid) msg_store<Msg>(msg + (size_t)ri.ref[k] * Z + a, out[k]);
+            } else {
+                const float lp = x[q][k] + out[k];  // posterior of the degree-1 variable
+                const unsigned long long bits = wave_ballot(valid && lp < 0.0f);
+                if ((threadIdx.x & 63) == 0 && valid)
+                    A.d1_cur[(size_t)f * A.d1_frame + (size_t)ri.ref[k] * c.W + w] = bits;
+                if (A.d1post && valid)
+                    A.d1post[(size_t)f * A.d1post_frame + (size_t)ri.ref[k] * Z + a] = lp;
+            }
+        }
+    }
+    return bad;
+}
+
+template <int D, typename Msg>
+__device__ __forceinline__ void check_row(const CodeDev &c, const CnArgs &A, int f, int r) {
+    const RowInfo<D> ri = load_row<D>(c, r);
+    constexpr int K = ChunkOf<D>::value;
+    const int a0 = blockIdx.x * (kBlock * kChecksPerThread) + threadIdx.x;
+    int bad = 0;
+#pragma unroll
+    for (int q0 = 0; q0 < kChecksPerThread; q0 += K)
+        bad |= check_chunk<D, K, Msg>(c, A, ri, f, r, a0 + q0 * kBlock);
+    if (A.vote) {
+        // One flag per frame and iteration, set by any workgroup holding an
+        // unsatisfied check.  Every writer stores the same value, so plain
+        // stores suffice; reading first keeps all but a few workgroups per
+        // frame from storing at all (the next launch sees the stores).
+        bad = __syncthreads_or(bad);
+        if (bad && threadIdx.x == 0) {
+            int32_t *flag = A.fail + (size_t)(A.update ? A.t - 1 : A.t) * A.F + f;
+            if (*reinterpret_cast<volatile int32_t *>(flag) == 0) *flag = 1;
         }
     }
 }
 
-template <typename Msg>
+// One launch covers the rows of one degree class; grid.y walks that class's
+// rows in the row list.
+template <typename Msg, bool kLarge>
 __global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A) {
     const int f = blockIdx.z;
-    const int r = blockIdx.y;
+    const int r = c.row_list[(kLarge ? c.n_small : 0) + (int)blockIdx.y];
     if (A.skip_after >= 0 && A.fail[(size_t)A.skip_after * A.F + f] == 0) return;
-    const int a = blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = a < c.Z;
-    switch (c.row_deg[r]) {
 #define LDPC_CASE(D) \
-    case D: check_update<D, Msg>(c, A, f, r, a, valid); break;
-        LDPC_CASE(1) LDPC_CASE(2) LDPC_CASE(3) LDPC_CASE(4) LDPC_CASE(5) LDPC_CASE(6)
-        LDPC_CASE(7) LDPC_CASE(8) LDPC_CASE(9) LDPC_CASE(10) LDPC_CASE(11) LDPC_CASE(12)
-        LDPC_CASE(13) LDPC_CASE(14) LDPC_CASE(15) LDPC_CASE(16)
-#undef LDPC_CASE
-        default: break;
+    case D: check_row<D, Msg>(c, A, f, r); break;
+    if (!kLarge) {
+        static_assert(kSmallRowDegree == 6, "case list below covers degrees 1..6");
+        switch (c.row_deg[r]) {
+            LDPC_CASE(1) LDPC_CASE(2) LDPC_CASE(3) LDPC_CASE(4) LDPC_CASE(5) LDPC_CASE(6)
+            default: break;
+        }
+    } else {
+        static_assert(LDPC_MAX_ROW_DEGREE == 16, "case list below covers degrees 7..16");
+        switch (c.row_deg[r]) {
+            LDPC_CASE(7) LDPC_CASE(8) LDPC_CASE(9) LDPC_CASE(10) LDPC_CASE(11) LDPC_CASE(12)
+            LDPC_CASE(13) LDPC_CASE(14) LDPC_CASE(15) LDPC_CASE(16)
+            default: break;
+        }
     }
+#undef LDPC_CASE
+}
+
+template <typename Msg>
+void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, hipStream_t st) {
+    const unsigned tiles_a = (unsigned)((c.Z + kBlock * kChecksPerThread - 1) / (kBlock * kChecksPerThread));
+    if (c.n_small > 0)
+        check_pass<Msg, false><<<dim3(tiles_a, c.n_small, F), dim3(kBlock), 0, st>>>(c, a);
+    if (c.n_large > 0)
+        check_pass<Msg, true><<<dim3(tiles_a, c.n_large, F), dim3(kBlock), 0, st>>>(c, a);
 }
 
 struct VnArgs {
@@ -215,7 +321,21 @@ __global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A) {
     const Msg *msg = reinterpret_cast<const Msg *>(A.msg) + (size_t)f * A.msg_frame;
     float L = A.llr[(size_t)f * c.n + (size_t)c.core_col[k] * Z + j];
     const int i0 = c.core_first[k], deg = c.core_deg[k];
-    for (int i = 0; i < deg; ++i) {
+    // loads issued 16 at a time, sums kept in increasing row order
+    constexpr int U = 16;
+    int i = 0;
+    for (; i + U <= deg; i += U) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int idx = j - c.core_shift[i0 + i + u];
+            idx += (idx < 0) ? Z : 0;
+            v[u] = msg_load<Msg>(msg + (size_t)c.core_state[i0 + i + u] * Z + idx);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) L += v[u];
+    }
+    for (; i < deg; ++i) {
         int idx = j - c.core_shift[i0 + i];
         idx += (idx < 0) ? Z : 0;
         L += msg_load<Msg>(msg + (size_t)c.core_state[i0 + i] * Z + idx);
@@ -363,7 +483,6 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     a.syn_frame = L.synbits_frame;
     a.d1post_frame = L.d1post_frame;
     a.F = F;
-    const dim3 cn_grid(tiles(c.Z), c.mb, F);
 
     VnArgs v{};
     v.llr = l.llr;
@@ -386,7 +505,7 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
         a.d1post = d1p[t & 1];
         a.skip_after = t >= 2 ? t - 2 : -1;
         if (l.events) (void)hipEventRecord(l.events[2 * (t - 1)], st);
-        check_pass<Msg><<<cn_grid, dim3(kBlock), 0, st>>>(c, a);
+        launch_check_pass<Msg>(c, a, F, st);
         if (l.events) (void)hipEventRecord(l.events[2 * (t - 1) + 1], st);
         if (c.NC > 0) {
             v.t = t;
@@ -404,7 +523,7 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     a.d1_cur = nullptr;
     a.d1post = nullptr;
     a.skip_after = T >= 1 ? T - 1 : -1;
-    check_pass<Msg><<<cn_grid, dim3(kBlock), 0, st>>>(c, a);
+    launch_check_pass<Msg>(c, a, F, st);
 
     FinArgs fa{};
     fa.llr = l.llr;

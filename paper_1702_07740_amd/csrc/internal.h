@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/ldpc.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -19,6 +21,11 @@ namespace ldpc {
 enum : int32_t { KIND_STATE = 0, KIND_DEG1 = 1 };
 enum : int32_t { COL_CORE = 0, COL_DEG1 = 1, COL_DEG0 = 2 };
 
+// Check rows up to this degree share one kernel; larger rows (up to
+// LDPC_MAX_ROW_DEGREE) get their own, so their register needs do not lower
+// the occupancy of the common low-degree rows.
+constexpr int kSmallRowDegree = 6;
+
 // Device view of a code: sizes plus pointers into small device tables.  Passed
 // by value as a kernel argument; every table index below is uniform across a
 // workgroup, so the loads are scalar.
@@ -31,6 +38,10 @@ struct CodeDev {
     // per base row r: blocks row_first[r] .. row_first[r] + row_deg[r] - 1,
     // in increasing column order
     const int32_t *row_first, *row_deg;
+    // base rows ordered by degree class: the n_small rows of degree
+    // <= kSmallRowDegree first, then the n_large others
+    const int32_t *row_list;
+    int32_t n_small, n_large;
     // per block: shift, kind, ref (state index or degree-1 index), column,
     // core index of the column (state blocks only, else -1)
     const int32_t *blk_shift, *blk_kind, *blk_ref, *blk_col, *blk_core;

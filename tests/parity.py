@@ -1,7 +1,11 @@
 """Shared parity checks: HIP decoder outputs against the FP64 oracle.
 
 Tolerances (stated once, used by every parity test):
-  * posterior LLRs: |L_gpu - L_ref| <= 1e-3 * max(|L_ref|, 1)   (FP32 messages)
+  * posterior LLRs: |L_gpu - L_ref| <= 1e-3 * max(|L_ref|, 1)   (FP32 messages),
+    held for every frame up to POSTERIOR_HORIZON iterations.  Near the BP
+    threshold the iteration is chaotic: rounding differences between FP32 and
+    FP64 grow from ~5e-6 at t = 10 to ~3e-4 at t = 30 and past 1e-3 after ~50
+    iterations, so later posteriors are compared through decisions instead;
   * syndromes and converged flags: bit-exact; converged <=> H x = s, with
     H x recomputed on the CPU by the oracle;
   * hard decisions: bit-exact on frames that converge on both sides;
@@ -11,6 +15,7 @@ Tolerances (stated once, used by every parity test):
 import numpy as np
 
 LLR_RTOL = 1e-3
+POSTERIOR_HORIZON = 30
 
 
 def llr_close(L_gpu, L_ref, rtol=LLR_RTOL):

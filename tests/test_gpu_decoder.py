@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_1702_07740_amd import synth
-from tests.parity import LLR_RTOL, check_decode_parity, llr_close
+from tests.parity import LLR_RTOL, POSTERIOR_HORIZON, check_decode_parity, llr_close
 from tests.qc_dense import random_tree_base
 
 pytestmark = pytest.mark.gpu
@@ -64,7 +64,7 @@ def test_syndrome_bit_exact(ldpc, oracle_mod, kind, Z):
 
 # ------------------------------------------------- per-iteration posteriors
 @pytest.mark.parametrize("snr", [-15.4, -13.0])
-@pytest.mark.parametrize("T", [1, 2, 5, 10])
+@pytest.mark.parametrize("T", [1, 2, 5, 10, 20, 30])
 def test_posterior_llr_per_iteration(ldpc, oracle_mod, snr, T):
     Z = 64
     base = synth.template_base(144, Z, seed=1)
@@ -99,9 +99,11 @@ def test_decode_parity_small_template(ldpc, oracle_mod, snr, F, seed):
     summ = check_decode_parity(o, Q, s, bits, it, conv, ref, T)
     print("summary", summ, flush=True)
     assert summ["gpu_only"] + summ["ref_only"] <= max(1, F // 8)
+    # exit posteriors of frames that stop at the same iteration, within the
+    # horizon where FP32 and FP64 trajectories are held to 1e-3 (t <= 30)
     both = np.logical_and(conv.astype(bool), ref[3])
     for f in np.nonzero(both)[0]:
-        if it[f] == ref[2][f]:
+        if it[f] == ref[2][f] and it[f] <= POSTERIOR_HORIZON:
             ok, worst, _ = llr_close(L[f], ref[1][f])
             assert ok, f"frame {f}: posterior worst {worst:.3g}"
 
@@ -245,10 +247,10 @@ def test_general_code_with_degree_0_and_degree_1_rows(ldpc, oracle_mod):
     base[3, [1, 3, 5, 7, 9, 11, 18]] = rng.integers(0, Z, 7)
     base[4, [0, 2, 4]] = rng.integers(0, Z, 3)
     base[5, [6, 8, 10]] = rng.integers(0, Z, 3)
-    # column 19 stays empty (degree 0)
+    # columns 16 and 19 stay empty (degree 0)
     g, o = _codes(ldpc, oracle_mod, base, Z)
     info = g.info
-    assert info["deg0_cols"] == 1 and info["max_row_degree"] == 16
+    assert info["deg0_cols"] == 2 and info["max_row_degree"] == 16
     x, Q = synth.biawgn_frames(o.n, 4, 0.0, seed=8)
     s = o.syndrome(x)
     _say("general code", base.shape, Z)
@@ -340,3 +342,24 @@ def test_full_size_converged_frames_match_oracle(full_code):
     summ = check_decode_parity(o, Q, s, bits, it, conv, ref, T)
     print("summary", summ, it, ref[2], flush=True)
     assert summ["both"] >= 1
+
+
+@pytest.mark.parametrize("D", [2, 3, 6, 16])
+def test_single_check_update_accuracy_over_the_phi_range(ldpc, oracle_mod, D):
+    """One iteration of one base row of degree D (every column has degree 1,
+    so L_v = Q_v + m_cv): the message m_cv for input magnitudes spanning
+    1e-9 .. 40, i.e. both clamps and every branch of the Phi evaluation."""
+    rng = np.random.default_rng(1000 + D)
+    Z = 4096
+    base = rng.integers(0, Z, size=(1, D)).astype(np.int32)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    mag = np.exp(rng.uniform(np.log(1e-9), np.log(40.0), size=(2, o.n)))
+    Q = (mag * rng.choice([-1.0, 1.0], size=(2, o.n))).astype(np.float32)
+    s = rng.integers(0, 2, size=(2, o.m)).astype(np.uint8)
+    _say("single check accuracy", D)
+    _, _, _, L = _gpu_decode(g, Q, s, 1, early_stop=False, want_llr=True)
+    _, L_r, _, _ = o.decode(Q, s, 1, early_stop=False)
+    m_r = L_r - Q.astype(np.float64)
+    err = np.abs(L.astype(np.float64) - L_r)
+    bound = 1e-5 * np.maximum(np.abs(L_r), np.abs(m_r)) + 1e-30
+    assert np.all(err <= bound), float(np.max(err / bound))
