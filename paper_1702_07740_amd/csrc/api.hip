@@ -112,12 +112,20 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     std::vector<int32_t> d1_shift(d1_col.size(), 0);
     std::vector<int32_t> st_row, st_core, st_shift;
     int maxdeg = 0;
+    std::vector<int32_t> row_ns(mb);
     for (int r = 0; r < mb; ++r) {
         row_first[r] = (int32_t)blk_shift.size();
         int d = 0;
-        for (int c = 0; c < nb; ++c) {
+        // within a row: blocks of stored columns first, then degree-1 blocks,
+        // each group in increasing column order
+        std::vector<int> cols;
+        for (int c = 0; c < nb; ++c)
+            if (base[(size_t)r * nb + c] >= 0 && col_kind[c] == ldpc::COL_CORE) cols.push_back(c);
+        row_ns[r] = (int32_t)cols.size();
+        for (int c = 0; c < nb; ++c)
+            if (base[(size_t)r * nb + c] >= 0 && col_kind[c] != ldpc::COL_CORE) cols.push_back(c);
+        for (int c : cols) {
             const int32_t s = base[(size_t)r * nb + c];
-            if (s < 0) continue;
             ++d;
             blk_shift.push_back(s);
             blk_col.push_back(c);
@@ -171,12 +179,13 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         host.push_back(0);  // keeps every table non-empty
         return off;
     };
-    const size_t o_row_first = put(row_first), o_row_deg = put(row_deg);
+    const size_t o_row_first = put(row_first), o_row_deg = put(row_deg), o_row_ns = put(row_ns);
     const size_t o_bs = put(blk_shift), o_bk = put(blk_kind), o_br = put(blk_ref),
                  o_bc = put(blk_col), o_bco = put(blk_core);
     const size_t o_cc = put(core_col), o_cf = put(core_first), o_cd = put(core_deg),
                  o_cs = put(core_state), o_csh = put(core_shift);
-    const size_t o_colk = put(col_kind), o_colr = put(col_ref), o_d1s = put(d1_shift);
+    const size_t o_colk = put(col_kind), o_colr = put(col_ref), o_d1s = put(d1_shift),
+                 o_d1c = put(d1_col);
     std::vector<int32_t> row_list;
     for (int r = 0; r < mb; ++r)
         if (row_deg[r] <= ldpc::kSmallRowDegree) row_list.push_back(r);
@@ -217,6 +226,7 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.W = (Z + 63) / 64;
     d.row_first = T + o_row_first;
     d.row_deg = T + o_row_deg;
+    d.row_ns = T + o_row_ns;
     d.row_list = T + o_rl;
     d.n_small = n_small;
     d.n_large = mb - n_small;
@@ -233,6 +243,7 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.col_kind = T + o_colk;
     d.col_ref = T + o_colr;
     d.d1_shift = T + o_d1s;
+    d.d1_col = T + o_d1c;
 
     ldpc_code_info_t &I = code->info;
     I.n = d.n;

@@ -1,7 +1,8 @@
 // Flooding sum-product decoding of QC LDPC codes in syndrome form, gfx950.
 //
 // One decode is a short sequence of launches on the caller's stream:
-//   init      fail flags, packed syndrome bits, core totals L = Q
+//   init      fail flags, packed syndrome bits, core totals L = Q, and the
+//             degree-1 inputs Psi = +-Phi(|Q|)
 //   t = 1..T  check pass (Alg. 1 Step 2, plus the Step 4 check of iteration
 //             t-1) and variable pass (Step 3, core columns)
 //   vote      the Step 4 check of the last iteration
@@ -14,8 +15,12 @@
 // wrap.  No index arrays exist: the circulant shift is the whole addressing.
 //
 // Degree-1 columns (the long diagonal, Sec. III-C) keep no state: their
-// variable-to-check message is the constant channel LLR, and their posterior
-// Q + m is formed in the check pass only for the decision bit, which is stored
+// variable-to-check message is the constant channel LLR Q, so Phi(|Q|) is
+// evaluated once per decode (Psi, stored in check order with the sign of Q).
+// Their posterior Q + m is needed only for the decision bit, and its sign
+// follows from the Phi domain without evaluating m: Phi is a decreasing
+// involution, so |Q| > |m| = Phi(S) exactly when Phi(|Q|) < S, where S is the
+// exclusive Phi sum of the check's other inputs.  The decision bits are stored
 // packed by check position (one bit per degree-1 block and check).
 //
 // Early stop.  Frame f's check for iteration t-1 is evaluated inside check
@@ -24,6 +29,9 @@
 // pass skips a frame whose earlier check succeeded; the variable pass t skips
 // a frame whose check at t-1 succeeded, so the frame's totals and degree-1 bits
 // stay those of its exit iteration.
+//
+// Addressing.  Every array is reached from a workgroup-uniform base pointer
+// plus a 32-bit lane offset, so loads and stores use the scalar-base form.
 #include "internal.h"
 
 #include <hip/hip_fp16.h>
@@ -36,41 +44,35 @@ constexpr int kBlock = 256;  // threads per workgroup: 4 wave64s
 constexpr float kPhiLo = 1e-7f;
 constexpr float kPhiHi = 30.0f;
 
-// Phi(x) = -ln tanh(x/2) on the clamped argument [1e-7, 30], from the
-// hardware base-2 exponential, logarithm and reciprocal:
-//   with t = e^{-x}, Phi(x) = ln((1 + t) / (1 - t)) = 2 atanh(t).
-//   x >= 1.5 (t <= 0.223): the odd series 2t (1 + t^2/3 + ... + t^10/11),
-//            truncation below 1e-8 relative, no cancellation for large x;
-//   x <  1.5: ln((2 - d) / d) with d = 1 - t, where d comes from the Taylor
-//            series of 1 - e^{-x} when x < 0.1 so that small x keeps its
-//            relative precision.
-// Relative error below 2e-6 over the whole range (below 3e-7 for x < 25).
+// Phi(x) = -ln tanh(x/2) on the clamped argument [1e-7, 30], branch-free:
+//   x <  2: Phi(x) = ln 2 - ln x + g(x^2/4), where g(u) = -ln(tanh(y)/y),
+//           y = sqrt(u), is smooth and even; g(w/4) = w H(w) with H a degree-6
+//           least-squares fit on [0, 4] (absolute error 3e-9);
+//   x >= 2: Phi(x) = 2 atanh(t), t = e^{-x} <= 0.136, by its odd series to t^9
+//           (truncation below 3e-10 relative; no cancellation for large x).
+// Both branches use one hardware transcendental (log2 or exp2).  Relative
+// error below 1e-6 for x < 20 and below 2e-6 up to 30 (there Phi < 2e-9).
 __device__ __forceinline__ float phi_f32(float x) {
     constexpr float kLog2e = 1.4426950408889634f;
     constexpr float kLn2 = 0.6931471805599453f;
-    x = fminf(fmaxf(x, kPhiLo), kPhiHi);
+    x = __builtin_amdgcn_fmed3f(x, kPhiLo, kPhiHi);
+    const float w = x * x;
+    float h = 5.28133137e-09f;
+    h = fmaf(w, h, -1.35732463e-07f);
+    h = fmaf(w, h, 2.02647516e-06f);
+    h = fmaf(w, h, -2.61091045e-05f);
+    h = fmaf(w, h, 3.41622334e-04f);
+    h = fmaf(w, h, -4.86108987e-03f);
+    h = fmaf(w, h, 8.33333358e-02f);
+    const float small = fmaf(-kLn2, __builtin_amdgcn_logf(x), kLn2) + w * h;
     const float t = __builtin_amdgcn_exp2f(-x * kLog2e);
-    if (x >= 1.5f) {
-        const float t2 = t * t;
-        float p = fmaf(t2, 1.0f / 11.0f, 1.0f / 9.0f);
-        p = fmaf(t2, p, 1.0f / 7.0f);
-        p = fmaf(t2, p, 1.0f / 5.0f);
-        p = fmaf(t2, p, 1.0f / 3.0f);
-        p = fmaf(t2, p, 1.0f);
-        return 2.0f * t * p;
-    }
-    float d;
-    if (x < 0.1f) {
-        float p = fmaf(x, 1.0f / 120.0f, -1.0f / 24.0f);
-        p = fmaf(x, p, 1.0f / 6.0f);
-        p = fmaf(x, p, -0.5f);
-        p = fmaf(x, p, 1.0f);
-        d = x * p;
-    } else {
-        d = 1.0f - t;
-    }
-    const float q = (2.0f - d) * __builtin_amdgcn_rcpf(d);
-    return __builtin_amdgcn_logf(q) * kLn2;
+    const float t2 = t * t;
+    float p = fmaf(t2, 2.0f / 9.0f, 2.0f / 7.0f);
+    p = fmaf(t2, p, 2.0f / 5.0f);
+    p = fmaf(t2, p, 2.0f / 3.0f);
+    p = fmaf(t2, p, 2.0f);
+    const float large = t * p;
+    return x < 2.0f ? small : large;
 }
 
 template <typename Msg> __device__ __forceinline__ float msg_load(const Msg *p);
@@ -86,8 +88,22 @@ template <> __device__ __forceinline__ void msg_store<_Float16>(_Float16 *p, flo
 
 __device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
 
+// Element idx of an array, with the byte offset formed in 32-bit arithmetic so
+// the access uses a uniform 64-bit base plus a 32-bit lane offset.  Every
+// per-frame array here is far below 4 GB.
+template <typename T>
+__device__ __forceinline__ T &at(T *base, unsigned idx) {
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T &at(const T *base, unsigned idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                        idx * (unsigned)sizeof(T));
+}
+
 struct CnArgs {
     const float *llr;          // [F][n]
+    const float *psi;          // [F][ND1][Z] +-Phi(|Q|) of degree-1 variables, check order
     void *msg;                 // [F][NS][Z] messages (float or half)
     const float *tot;          // [F][NC][Z] core totals of iteration t-1
     const uint64_t *d1_prev;   // [F][ND1][W] degree-1 decision bits of iteration t-1
@@ -95,7 +111,7 @@ struct CnArgs {
     const uint64_t *synbits;   // [F][mb][W]
     int32_t *fail;             // [T+1][F]
     float *d1post;             // [F][ND1][Z] degree-1 posteriors of iteration t, or null
-    size_t msg_frame, tot_frame, d1_frame, syn_frame, d1post_frame;
+    size_t msg_frame, tot_frame, d1_frame, syn_frame, psi_frame;
     int F, t;
     int update;                // 1: compute the messages of iteration t
     int first;                 // 1: t == 1, all stored messages are zero
@@ -104,30 +120,61 @@ struct CnArgs {
     int skip_after;            // frame inactive if fail[skip_after][f] == 0 (-1: never)
 };
 
-// Per-row block data, uniform across a workgroup (scalar registers).
-template <int D>
-struct RowInfo {
-    int shift[D];        // circulant shift of each block
-    int ref[D];          // state index (stored blocks) or degree-1 index
-    int src[D];          // core index (stored blocks) or base column (degree-1)
-    unsigned state_mask; // bit k set: block k keeps stored messages
+// Workgroup-uniform view of one base row of one frame.
+template <int D, typename Msg>
+struct RowCtx {
+    const float *tot;         // frame's core totals
+    Msg *msg;                 // frame's messages
+    const float *psi;         // frame's degree-1 inputs
+    const float *llr;         // frame's channel LLRs
+    const uint64_t *d1_prev;  // frame's decision bits of iteration t-1
+    uint64_t *d1_cur;         // frame's decision bits of iteration t
+    float *d1post;            // frame's degree-1 posteriors (or null)
+    const uint64_t *syn;      // this row's packed syndrome words
+    unsigned shift[D];        // circulant shift of each block
+    unsigned off[D];          // state: msg offset ref*Z; degree-1: psi offset ref*Z
+    unsigned src[D];          // state: totals offset core*Z; degree-1: llr offset col*Z
+    unsigned wrd[D];          // degree-1: decision-word offset ref*W
+    int ns;                   // blocks 0..ns-1 keep stored messages, the rest are degree-1
+    unsigned Z, W;
 };
 
-template <int D>
-__device__ __forceinline__ RowInfo<D> load_row(const CodeDev &c, int r) {
-    RowInfo<D> ri;
+template <int D, typename Msg>
+__device__ __forceinline__ RowCtx<D, Msg> load_row(const CodeDev &c, const CnArgs &A, int f,
+                                                   int r) {
+    RowCtx<D, Msg> R;
+    const unsigned Z = (unsigned)c.Z;
+    R.Z = Z;
+    R.W = (unsigned)c.W;
+    R.tot = A.tot + (size_t)f * A.tot_frame;
+    R.msg = reinterpret_cast<Msg *>(A.msg) + (size_t)f * A.msg_frame;
+    R.psi = A.psi + (size_t)f * A.psi_frame;
+    R.llr = A.llr + (size_t)f * c.n;
+    R.d1_prev = A.d1_prev + (size_t)f * A.d1_frame;
+    R.d1_cur = A.d1_cur ? A.d1_cur + (size_t)f * A.d1_frame : nullptr;
+    R.d1post = A.d1post ? A.d1post + (size_t)f * A.psi_frame : nullptr;
+    R.syn = A.synbits + (size_t)f * A.syn_frame + (size_t)r * c.W;
     const int b0 = c.row_first[r];
-    ri.state_mask = 0;
+    R.ns = c.row_ns[r];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const int b = b0 + k;
-        const bool st = c.blk_kind[b] == KIND_STATE;
-        ri.shift[k] = c.blk_shift[b];
-        ri.ref[k] = c.blk_ref[b];
-        ri.src[k] = st ? c.blk_core[b] : c.blk_col[b];
-        ri.state_mask |= (unsigned)st << k;
+        const bool st = k < R.ns;
+        const unsigned ref = (unsigned)c.blk_ref[b];
+        R.shift[k] = (unsigned)c.blk_shift[b];
+        R.off[k] = ref * Z;
+        R.src[k] = (unsigned)(st ? c.blk_core[b] : c.blk_col[b]) * Z;
+        R.wrd[k] = ref * R.W;
     }
-    return ri;
+    return R;
+}
+
+// Is block k of a row with DS stored blocks a stored block?  DS >= 0 is known
+// at compile time; DS < 0 reads the row's count.
+template <int DS, int D, typename Msg>
+__device__ __forceinline__ bool stored(const RowCtx<D, Msg> &R, int k) {
+    if constexpr (DS >= 0) return k < DS;
+    else return k < R.ns;
 }
 
 // Checks per thread: a thread handles checks a, a + 256, a + 512, a + 768 of
@@ -135,56 +182,46 @@ __device__ __forceinline__ RowInfo<D> load_row(const CodeDev &c, int r) {
 // loads for several checks in flight together.
 constexpr int kChecksPerThread = 4;
 // how many of those are processed at once (bounded by registers for large D)
-template <int D> struct ChunkOf { static constexpr int value = D <= 4 ? 4 : (D <= 8 ? 2 : 1); };
+template <int D> struct ChunkOf { static constexpr int value = D <= 4 ? 2 : 1; };
 
 // K checks (r, a_first + q*256), q < K, of one frame, row degree D.  Padding
 // lanes (a >= Z) take part in the wave ballots with zero bits and touch no
 // memory.  Returns 1 if one of this thread's checks fails the parity check of
 // the voted iteration.
-template <int D, int K, typename Msg>
-__device__ __forceinline__ int check_chunk(const CodeDev &c, const CnArgs &A, const RowInfo<D> &ri,
-                                           int f, int r, int a_first) {
-    const int Z = c.Z;
-    const float *llr = A.llr + (size_t)f * c.n;
-    const float *tot = A.tot + (size_t)f * A.tot_frame;
-    Msg *msg = reinterpret_cast<Msg *>(A.msg) + (size_t)f * A.msg_frame;
-    const uint64_t *syn = A.synbits + (size_t)f * A.syn_frame + (size_t)r * c.W;
+template <int D, int DS, int K, typename Msg>
+__device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs &A,
+                                           unsigned a_first) {
+    const unsigned Z = R.Z;
     const bool read_old = A.update && !A.first;
 
-    float x[K][D];  // variable-to-check inputs L_vc of iteration t-1
-    int vpar[K];    // parity of the voted decisions on each check, with s_c
-    int sb[K];      // syndrome bits
+    float x[K][D];   // inputs L_vc of iteration t-1 (degree-1: Psi)
+    int vpar[K];     // parity of the voted decisions on each check, with s_c
+    int sb[K];       // syndrome bits
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-        const int a = a_first + q * kBlock;
+        const unsigned a = a_first + q * kBlock;
         const bool valid = a < Z;
-        const int w = a >> 6, bit = a & 63;
-        sb[q] = valid ? (int)((syn[w] >> bit) & 1ull) : 0;
+        const unsigned w = a >> 6, bit = a & 63u;
+        sb[q] = valid ? (int)((at(R.syn, w) >> bit) & 1ull) : 0;
         int par = 0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            int j = a + ri.shift[k];
-            j -= (j >= Z) ? Z : 0;
+            unsigned j = a + R.shift[k];
+            j -= (j >= Z) ? Z : 0u;
             float xv = 1.0f;
             int dec = 0;
-            if ((ri.state_mask >> k) & 1u) {
+            if (stored<DS>(R, k)) {
                 if (valid) {
-                    const float lt = tot[(size_t)ri.src[k] * Z + j];
+                    const float lt = at(R.tot, R.src[k] + j);
                     dec = lt < 0.0f;
-                    const float mo = read_old ? msg_load<Msg>(msg + (size_t)ri.ref[k] * Z + a) : 0.0f;
+                    const float mo = read_old ? msg_load<Msg>(&at(R.msg, R.off[k] + a)) : 0.0f;
                     xv = lt - mo;
                 }
             } else if (valid) {
-                xv = llr[(size_t)ri.src[k] * Z + j];
-                if (A.vote) {
-                    if (A.d1_from_llr) {
-                        dec = xv < 0.0f;
-                    } else {
-                        const uint64_t wd =
-                            A.d1_prev[(size_t)f * A.d1_frame + (size_t)ri.ref[k] * c.W + w];
-                        dec = (int)((wd >> bit) & 1ull);
-                    }
-                }
+                xv = at(R.psi, R.off[k] + a);
+                if (A.vote)
+                    dec = A.d1_from_llr ? (xv < 0.0f)
+                                        : (int)((at(R.d1_prev, R.wrd[k] + w) >> bit) & 1ull);
             }
             x[q][k] = xv;
             par ^= dec;
@@ -200,9 +237,9 @@ __device__ __forceinline__ int check_chunk(const CodeDev &c, const CnArgs &A, co
 
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-        const int a = a_first + q * kBlock;
+        const unsigned a = a_first + q * kBlock;
         const bool valid = a < Z;
-        const int w = a >> 6;
+        const unsigned w = a >> 6;
         // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
         float ph[D];
         int neg = 0, par = sb[q];
@@ -211,46 +248,53 @@ __device__ __forceinline__ int check_chunk(const CodeDev &c, const CnArgs &A, co
             const int nk = x[q][k] < 0.0f;
             neg |= nk << k;
             par ^= nk;
-            ph[k] = phi_f32(fabsf(x[q][k]));
+            ph[k] = stored<DS>(R, k) ? phi_f32(fabsf(x[q][k])) : fabsf(x[q][k]);
         }
         float pre[D];
         pre[0] = 0.0f;
 #pragma unroll
         for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + ph[k - 1];
+        float ex[D];
         float suf = 0.0f;
-        float out[D];
 #pragma unroll
         for (int k = D - 1; k >= 0; --k) {
-            const float mag = phi_f32(pre[k] + suf);
+            ex[k] = pre[k] + suf;
             suf += ph[k];
-            out[k] = ((par ^ (neg >> k)) & 1) ? -mag : mag;
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            if ((ri.state_mask >> k) & 1u) {
-                if (valid) msg_store<Msg>(msg + (size_t)ri.ref[k] * Z + a, out[k]);
+            const int sgn = (par ^ (neg >> k)) & 1;  // 1: the message to block k is negative
+            if (stored<DS>(R, k)) {
+                const float mag = phi_f32(ex[k]);
+                if (valid) msg_store<Msg>(&at(R.msg, R.off[k] + a), sgn ? -mag : mag);
             } else {
-                const float lp = x[q][k] + out[k];  // posterior of the degree-1 variable
-                const unsigned long long bits = wave_ballot(valid && lp < 0.0f);
-                if ((threadIdx.x & 63) == 0 && valid)
-                    A.d1_cur[(size_t)f * A.d1_frame + (size_t)ri.ref[k] * c.W + w] = bits;
-                if (A.d1post && valid)
-                    A.d1post[(size_t)f * A.d1post_frame + (size_t)ri.ref[k] * Z + a] = lp;
+                // decision of the degree-1 variable: sign of Q + m
+                const int negq = (neg >> k) & 1;
+                const float S = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, kPhiHi);
+                const int dec = (negq == sgn) ? negq : (ph[k] < S ? negq : sgn);
+                const unsigned long long bits = wave_ballot(valid && dec);
+                if ((threadIdx.x & 63) == 0 && valid) at(R.d1_cur, R.wrd[k] + w) = bits;
+                if (R.d1post && valid) {
+                    unsigned j = a + R.shift[k];
+                    j -= (j >= Z) ? Z : 0u;
+                    const float mag = phi_f32(ex[k]);
+                    at(R.d1post, R.off[k] + a) = at(R.llr, R.src[k] + j) + (sgn ? -mag : mag);
+                }
             }
         }
     }
     return bad;
 }
 
-template <int D, typename Msg>
+template <int D, int DS, typename Msg>
 __device__ __forceinline__ void check_row(const CodeDev &c, const CnArgs &A, int f, int r) {
-    const RowInfo<D> ri = load_row<D>(c, r);
+    const RowCtx<D, Msg> R = load_row<D, Msg>(c, A, f, r);
     constexpr int K = ChunkOf<D>::value;
-    const int a0 = blockIdx.x * (kBlock * kChecksPerThread) + threadIdx.x;
+    const unsigned a0 = blockIdx.x * (kBlock * kChecksPerThread) + threadIdx.x;
     int bad = 0;
 #pragma unroll
     for (int q0 = 0; q0 < kChecksPerThread; q0 += K)
-        bad |= check_chunk<D, K, Msg>(c, A, ri, f, r, a0 + q0 * kBlock);
+        bad |= check_chunk<D, DS, K, Msg>(R, A, a0 + q0 * kBlock);
     if (A.vote) {
         // One flag per frame and iteration, set by any workgroup holding an
         // unsatisfied check.  Every writer stores the same value, so plain
@@ -265,18 +309,28 @@ __device__ __forceinline__ void check_row(const CodeDev &c, const CnArgs &A, int
 }
 
 // One launch covers the rows of one degree class; grid.y walks that class's
-// rows in the row list.
+// rows in the row list.  Small rows are compiled for every (degree, stored
+// blocks) pair, large rows for every degree with the split read at run time.
 template <typename Msg, bool kLarge>
 __global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A) {
     const int f = blockIdx.z;
     const int r = c.row_list[(kLarge ? c.n_small : 0) + (int)blockIdx.y];
     if (A.skip_after >= 0 && A.fail[(size_t)A.skip_after * A.F + f] == 0) return;
 #define LDPC_CASE(D) \
-    case D: check_row<D, Msg>(c, A, f, r); break;
+    case D: check_row<D, -1, Msg>(c, A, f, r); break;
+#define LDPC_CASE2(D, S) \
+    case (D) * 32 + (S): check_row<D, S, Msg>(c, A, f, r); break;
     if (!kLarge) {
         static_assert(kSmallRowDegree == 6, "case list below covers degrees 1..6");
-        switch (c.row_deg[r]) {
-            LDPC_CASE(1) LDPC_CASE(2) LDPC_CASE(3) LDPC_CASE(4) LDPC_CASE(5) LDPC_CASE(6)
+        switch (c.row_deg[r] * 32 + c.row_ns[r]) {
+            LDPC_CASE2(1, 0) LDPC_CASE2(1, 1)
+            LDPC_CASE2(2, 0) LDPC_CASE2(2, 1) LDPC_CASE2(2, 2)
+            LDPC_CASE2(3, 0) LDPC_CASE2(3, 1) LDPC_CASE2(3, 2) LDPC_CASE2(3, 3)
+            LDPC_CASE2(4, 0) LDPC_CASE2(4, 1) LDPC_CASE2(4, 2) LDPC_CASE2(4, 3) LDPC_CASE2(4, 4)
+            LDPC_CASE2(5, 0) LDPC_CASE2(5, 1) LDPC_CASE2(5, 2) LDPC_CASE2(5, 3) LDPC_CASE2(5, 4)
+            LDPC_CASE2(5, 5)
+            LDPC_CASE2(6, 0) LDPC_CASE2(6, 1) LDPC_CASE2(6, 2) LDPC_CASE2(6, 3) LDPC_CASE2(6, 4)
+            LDPC_CASE2(6, 5) LDPC_CASE2(6, 6)
             default: break;
         }
     } else {
@@ -288,11 +342,13 @@ __global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A) {
         }
     }
 #undef LDPC_CASE
+#undef LDPC_CASE2
 }
 
 template <typename Msg>
 void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, hipStream_t st) {
-    const unsigned tiles_a = (unsigned)((c.Z + kBlock * kChecksPerThread - 1) / (kBlock * kChecksPerThread));
+    const unsigned tiles_a =
+        (unsigned)((c.Z + kBlock * kChecksPerThread - 1) / (kBlock * kChecksPerThread));
     if (c.n_small > 0)
         check_pass<Msg, false><<<dim3(tiles_a, c.n_small, F), dim3(kBlock), 0, st>>>(c, a);
     if (c.n_large > 0)
@@ -315,11 +371,12 @@ __global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A) {
     const int f = blockIdx.z;
     const int k = blockIdx.y;
     if (A.fail[(size_t)(A.t - 1) * A.F + f] == 0) return;
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    const int Z = c.Z;
+    const unsigned Z = (unsigned)c.Z;
+    const unsigned j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= Z) return;
     const Msg *msg = reinterpret_cast<const Msg *>(A.msg) + (size_t)f * A.msg_frame;
-    float L = A.llr[(size_t)f * c.n + (size_t)c.core_col[k] * Z + j];
+    const float *llr = A.llr + (size_t)f * c.n + (size_t)c.core_col[k] * Z;
+    float L = llr[j];
     const int i0 = c.core_first[k], deg = c.core_deg[k];
     // loads issued 16 at a time, sums kept in increasing row order
     constexpr int U = 16;
@@ -328,17 +385,17 @@ __global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A) {
         float v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int idx = j - c.core_shift[i0 + i + u];
-            idx += (idx < 0) ? Z : 0;
-            v[u] = msg_load<Msg>(msg + (size_t)c.core_state[i0 + i + u] * Z + idx);
+            const unsigned s = (unsigned)c.core_shift[i0 + i + u];
+            const unsigned idx = (j >= s) ? j - s : j + Z - s;
+            v[u] = msg_load<Msg>(msg + (unsigned)c.core_state[i0 + i + u] * Z + idx);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) L += v[u];
     }
     for (; i < deg; ++i) {
-        int idx = j - c.core_shift[i0 + i];
-        idx += (idx < 0) ? Z : 0;
-        L += msg_load<Msg>(msg + (size_t)c.core_state[i0 + i] * Z + idx);
+        const unsigned s = (unsigned)c.core_shift[i0 + i];
+        const unsigned idx = (j >= s) ? j - s : j + Z - s;
+        L += msg_load<Msg>(msg + (unsigned)c.core_state[i0 + i] * Z + idx);
     }
     A.tot[(size_t)f * A.tot_frame + (size_t)k * Z + j] = L;
 }
@@ -374,6 +431,21 @@ __global__ __launch_bounds__(kBlock) void init_totals(CodeDev c, const float *ll
         llr[(size_t)f * c.n + (size_t)c.core_col[k] * c.Z + j];
 }
 
+// Degree-1 inputs in check order: Psi[a] = +-Phi(|Q_p|), p the variable of
+// check a of degree-1 block k, with the sign of Q_p (negative iff Q_p < 0).
+__global__ __launch_bounds__(kBlock) void init_psi(CodeDev c, const float *llr, float *psi,
+                                                   size_t psi_frame) {
+    const int f = blockIdx.z, k = blockIdx.y;
+    const unsigned Z = (unsigned)c.Z;
+    const unsigned a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= Z) return;
+    unsigned j = a + (unsigned)c.d1_shift[k];
+    j -= (j >= Z) ? Z : 0u;
+    const float q = llr[(size_t)f * c.n + (size_t)c.d1_col[k] * Z + j];
+    const float p = phi_f32(fabsf(q));
+    psi[(size_t)f * psi_frame + (size_t)k * Z + a] = q < 0.0f ? -p : p;
+}
+
 struct FinArgs {
     const float *llr;
     const float *tot;
@@ -384,7 +456,7 @@ struct FinArgs {
     int32_t *iters_out;
     uint8_t *conv_out;
     float *llr_out;
-    size_t tot_frame, d1_frame, d1post_frame;
+    size_t tot_frame, d1_frame, psi_frame;
     int F, T;
 };
 
@@ -418,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void finalize(CodeDev c, FinArgs A) {
         a += (a < 0) ? Z : 0;
         const uint64_t wd = A.d1bits[it & 1][(size_t)f * A.d1_frame + (size_t)ref * c.W + (a >> 6)];
         bit = (int)((wd >> (a & 63)) & 1ull);
-        if (A.llr_out) L = A.d1post[it & 1][(size_t)f * A.d1post_frame + (size_t)ref * Z + a];
+        if (A.llr_out) L = A.d1post[it & 1][(size_t)f * A.psi_frame + (size_t)ref * Z + a];
     }
     A.bits_out[(size_t)f * c.n + v] = (uint8_t)bit;
     if (A.llr_out) A.llr_out[(size_t)f * c.n + v] = L;
@@ -450,6 +522,7 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     char *ws = l.ws;
     void *msg = ws + L.msg;
     float *tot = reinterpret_cast<float *>(ws + L.tot);
+    float *psi = reinterpret_cast<float *>(ws + L.psi);
     uint64_t *d1b[2] = {reinterpret_cast<uint64_t *>(ws + L.d1bits),
                         reinterpret_cast<uint64_t *>(ws + L.d1bits) + (size_t)F * L.d1bits_frame};
     uint64_t *synbits = reinterpret_cast<uint64_t *>(ws + L.synbits);
@@ -457,7 +530,7 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     float *d1p[2] = {nullptr, nullptr};
     if (l.llr_out) {
         d1p[0] = reinterpret_cast<float *>(ws + L.d1post);
-        d1p[1] = d1p[0] + (size_t)F * L.d1post_frame;
+        d1p[1] = d1p[0] + (size_t)F * L.psi_frame;
     }
     hipStream_t st = l.stream;
 
@@ -468,11 +541,14 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
                                                                      L.synbits_frame);
     if (c.NC > 0)
         init_totals<<<dim3(tiles(c.Z), c.NC, F), dim3(kBlock), 0, st>>>(c, l.llr, tot, L.tot_frame);
+    if (c.ND1 > 0)
+        init_psi<<<dim3(tiles(c.Z), c.ND1, F), dim3(kBlock), 0, st>>>(c, l.llr, psi, L.psi_frame);
 
     auto checked = [&](int t) { return t == T || (l.early_stop && t >= l.check_from); };
 
     CnArgs a{};
     a.llr = l.llr;
+    a.psi = psi;
     a.msg = msg;
     a.tot = tot;
     a.synbits = synbits;
@@ -481,7 +557,7 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     a.tot_frame = L.tot_frame;
     a.d1_frame = L.d1bits_frame;
     a.syn_frame = L.synbits_frame;
-    a.d1post_frame = L.d1post_frame;
+    a.psi_frame = L.psi_frame;
     a.F = F;
 
     VnArgs v{};
@@ -539,7 +615,7 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     fa.llr_out = l.llr_out;
     fa.tot_frame = L.tot_frame;
     fa.d1_frame = L.d1bits_frame;
-    fa.d1post_frame = L.d1post_frame;
+    fa.psi_frame = L.psi_frame;
     fa.F = F;
     fa.T = T;
     finalize<<<dim3(tiles(c.n), F), dim3(kBlock), 0, st>>>(c, fa);
@@ -555,12 +631,14 @@ WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr)
     L.tot_frame = (size_t)c.NC * Z;
     L.d1bits_frame = (size_t)c.ND1 * c.W;
     L.synbits_frame = (size_t)c.mb * c.W;
-    L.d1post_frame = (size_t)c.ND1 * Z;
+    L.psi_frame = (size_t)c.ND1 * Z;
     size_t off = 0;
     L.msg = off;
     off = align256(off + (size_t)F * L.msg_frame * (fp16 ? 2 : 4));
     L.tot = off;
     off = align256(off + (size_t)F * L.tot_frame * 4);
+    L.psi = off;
+    off = align256(off + (size_t)F * L.psi_frame * 4);
     L.d1bits = off;
     off = align256(off + 2 * (size_t)F * L.d1bits_frame * 8);
     L.synbits = off;
@@ -568,7 +646,7 @@ WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr)
     L.fail = off;
     off = align256(off + (size_t)(T + 1) * F * 4);
     L.d1post = off;
-    if (want_llr) off = align256(off + 2 * (size_t)F * L.d1post_frame * 4);
+    if (want_llr) off = align256(off + 2 * (size_t)F * L.psi_frame * 4);
     L.total = off;
     return L;
 }

@@ -35,9 +35,10 @@ struct CodeDev {
     int32_t NC;   // core columns (degree >= 2)
     int32_t ND1;  // degree-1 columns (= degree-1 blocks)
     int32_t W;    // 64-bit words per Z bits
-    // per base row r: blocks row_first[r] .. row_first[r] + row_deg[r] - 1,
-    // in increasing column order
-    const int32_t *row_first, *row_deg;
+    // per base row r: blocks row_first[r] .. row_first[r] + row_deg[r] - 1;
+    // the first row_ns[r] are blocks of columns of degree >= 2 (stored
+    // messages), the rest degree-1 blocks, each group in column order
+    const int32_t *row_first, *row_deg, *row_ns;
     // base rows ordered by degree class: the n_small rows of degree
     // <= kSmallRowDegree first, then the n_large others
     const int32_t *row_list;
@@ -51,18 +52,18 @@ struct CodeDev {
     const int32_t *core_col, *core_first, *core_deg, *core_state, *core_shift;
     // per base column: kind and index within its kind
     const int32_t *col_kind, *col_ref;
-    // per degree-1 column: shift of its only block
-    const int32_t *d1_shift;
+    // per degree-1 column: its base column and the shift of its only block
+    const int32_t *d1_col, *d1_shift;
 };
 
 // Byte offsets of the decode workspace for F frames and T iterations.
 struct WorkLayout {
-    size_t msg, tot, d1bits, synbits, fail, d1post, total;
+    size_t msg, tot, psi, d1bits, synbits, fail, d1post, total;
     size_t msg_frame;      // elements per frame
     size_t tot_frame;      // floats per frame
+    size_t psi_frame;      // floats per frame (degree-1 inputs; also posteriors)
     size_t d1bits_frame;   // words per frame
     size_t synbits_frame;  // words per frame
-    size_t d1post_frame;   // floats per frame
 };
 
 WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr);

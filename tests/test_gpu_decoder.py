@@ -80,7 +80,10 @@ def test_posterior_llr_per_iteration(ldpc, oracle_mod, snr, T):
     margin = 2 * LLR_RTOL * np.maximum(np.abs(L_r), 1.0)
     sure = np.abs(L_r) > margin
     assert np.array_equal(bits[sure], b_r[sure])
-    assert np.array_equal(bits, (L < 0).astype(np.uint8))
+    # decisions follow the posterior sign, except within rounding of a tie
+    # (degree-1 decisions are taken in the Phi domain, see the decoder notes)
+    tie = np.abs(L) <= 1e-5 * np.maximum(np.abs(Q), 1.0)
+    assert np.all((bits == (L < 0)) | tie)
 
 
 # --------------------------------------------------- early-stop decoding

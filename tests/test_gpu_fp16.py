@@ -1,0 +1,108 @@
+"""FP16 message storage (arithmetic and sums in FP32) against FP32 and the oracle.
+
+Frame error rates are compared statistically (95% Wilson intervals); the FER
+of these template codes has no paper number, so this part is parity unpinned.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1702_07740_amd import synth
+from tests.parity import check_decode_parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ldpc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_07740_amd import ldpc as mod
+    mod.load()
+    return mod
+
+
+def wilson(k, n, z=1.959964):
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / d
+    return max(0.0, c - h), min(1.0, c + h)
+
+
+def _gpu(g, Q, s, T, fp16, **kw):
+    bits, it, conv, L = g.decode(torch.from_numpy(Q).cuda(), torch.from_numpy(s).cuda(), T,
+                                 msg_fp16=fp16, **kw)
+    torch.cuda.synchronize()
+    return bits.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy(), (None if L is None else L.cpu().numpy())
+
+
+def test_fp16_frame_error_rate_matches_fp32_and_oracle(ldpc, oracle_mod):
+    Z, T, F = 64, 100, 160
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    x, Q = synth.biawgn_frames(o.n, F, -14.0, seed=77)
+    s = o.syndrome(x)
+    _say("fp16 FER", F, "frames")
+    b32, i32, c32, _ = _gpu(g, Q, s, T, False)
+    b16, i16, c16, _ = _gpu(g, Q, s, T, True)
+    ref = o.decode(Q, s, T, threads=8)
+    # FP32 keeps the full parity contract
+    check_decode_parity(o, Q, s, b32, i32, c32, ref, T)
+    # FP16: flags are still exact (H x = s recomputed), decisions of frames
+    # that converge on both sides still agree bit for bit
+    syn = o.syndrome(b16)
+    for f in range(F):
+        assert bool(c16[f]) == np.array_equal(syn[f], s[f])
+    err = {name: int(np.sum(np.any(b != x, axis=1))) for name, b in
+           (("fp64", ref[0]), ("fp32", b32), ("fp16", b16))}
+    ci = {k: wilson(v, F) for k, v in err.items()}
+    print("frame errors", err, "95% CI", ci, flush=True)
+    assert 0 < err["fp64"] < F  # a waterfall point: FER strictly between 0 and 1
+    lo = max(ci["fp64"][0], ci["fp16"][0])
+    hi = min(ci["fp64"][1], ci["fp16"][1])
+    assert lo <= hi, "FP16 and FP64 frame error rates differ at 95%"
+    both = np.logical_and(c16.astype(bool), ref[3])
+    same = [np.array_equal(b16[f], ref[0][f]) for f in np.nonzero(both)[0]]
+    assert np.mean(same) >= 0.95
+
+
+def test_fp16_posteriors_track_fp32(ldpc, oracle_mod):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    x, Q = synth.biawgn_frames(o.n, 4, -15.4, seed=5)
+    s = o.syndrome(x)
+    _say("fp16 posteriors")
+    for T in (1, 3, 10):
+        _, _, _, L16 = _gpu(g, Q, s, T, True, early_stop=False, want_llr=True)
+        _, L_r, _, _ = o.decode(Q, s, T, early_stop=False)
+        rel = np.max(np.abs(L16 - L_r) / np.maximum(np.abs(L_r), 1.0))
+        print("T", T, "fp16 worst rel err", rel, flush=True)
+        assert rel < 2e-2
+
+
+def test_fp16_deterministic_and_batch_independent(ldpc, oracle_mod):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    x, Q = synth.biawgn_frames(o.n, 5, -13.5, seed=8)
+    s = o.syndrome(x)
+    _say("fp16 determinism")
+    r1 = _gpu(g, Q, s, 60, True, want_llr=True)
+    r2 = _gpu(g, Q, s, 60, True, want_llr=True)
+    for u, v in zip(r1, r2):
+        assert np.array_equal(u, v)
+    alone = _gpu(g, Q[2:3], s[2:3], 60, True, want_llr=True)
+    for u, v in zip(alone, r1):
+        assert np.array_equal(u[0], v[2])
