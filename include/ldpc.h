@@ -151,6 +151,37 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F,
 int ldpc_syndrome(const ldpc_code *code, int32_t F, const uint8_t *bits, uint8_t *syn_out,
                   void *stream);
 
+/*
+ * Multi-dimensional reverse reconciliation front-end (Sec. II-C.3): channel
+ * LLRs from Alice's samples X and Bob's public message M.
+ * Frames are cut into d-tuples, d in {1, 2, 4, 8} (reals, complex numbers,
+ * quaternions, octonions, multiplied by Cayley-Dickson doubling:
+ * (a, b)(c, e) = (a c - conj(e) b, e a + b conj(c))).  Per tuple Alice forms
+ * R = M X^{-1}; the noise of R has per-coordinate variance d sigma2 / |X|^2,
+ * so the LLR of coordinate i is 2 R_i |X|^2 / (d sigma2) = 2 (M conj(X))_i / (d sigma2).
+ *   d        1, 2, 4 or 8
+ *   F, n     frames and code length; every frame holds n_d = d * ceil(n / d)
+ *            samples (the last tuple is padded)
+ *   x, m     device [F][n_d] float32: Alice's samples and Bob's message
+ *   sigma2   channel noise variance sigma_Z^2 (SNR = 1 / sigma2), > 0
+ *   llr_out  device [F][n] float32: LLRs of the first n coordinates, ready for
+ *            ldpc_decode_batch
+ * Errors: LDPC_EINVAL (d, F, n, sigma2 or a null pointer), LDPC_EDEVICE.
+ */
+int ldpc_reconciliation_llr(int32_t d, int32_t F, int32_t n, const float *x, const float *m,
+                            float sigma2, float *llr_out, void *stream);
+
+/*
+ * Bob's side of the same scheme (Sec. II-C.3): M = U Y per d-tuple, with
+ * U_i = (-1)^{c_i}; coordinates of the padded last tuple take c = 0.
+ *   bits   device [F][n] uint8 key bits c (bit 0 used)
+ *   y      device [F][n_d] float32 Bob's samples
+ *   m_out  device [F][n_d] float32
+ * Errors: LDPC_EINVAL, LDPC_EDEVICE.
+ */
+int ldpc_reconciliation_message(int32_t d, int32_t F, int32_t n, const uint8_t *bits,
+                                const float *y, float *m_out, void *stream);
+
 /* Static English text for a status code. */
 const char *ldpc_status_string(int status);
 

@@ -186,12 +186,16 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
                  o_cs = put(core_state), o_csh = put(core_shift);
     const size_t o_colk = put(col_kind), o_colr = put(col_ref), o_d1s = put(d1_shift),
                  o_d1c = put(d1_col);
+    // common rows first: degree <= kSmallRowDegree with at most one degree-1 block
+    auto common = [&](int r) {
+        return row_deg[r] <= ldpc::kSmallRowDegree && row_ns[r] >= row_deg[r] - 1;
+    };
     std::vector<int32_t> row_list;
     for (int r = 0; r < mb; ++r)
-        if (row_deg[r] <= ldpc::kSmallRowDegree) row_list.push_back(r);
+        if (common(r)) row_list.push_back(r);
     const int n_small = (int)row_list.size();
     for (int r = 0; r < mb; ++r)
-        if (row_deg[r] > ldpc::kSmallRowDegree) row_list.push_back(r);
+        if (!common(r)) row_list.push_back(r);
     const size_t o_rl = put(row_list);
 
     ldpc_code *code = new (std::nothrow) ldpc_code();
@@ -340,6 +344,33 @@ int ldpc_syndrome(const ldpc_code *code, int32_t F, const uint8_t *bits, uint8_t
     if (st != LDPC_OK) return st;
     hipError_t e = ldpc::enqueue_syndrome(code->dev, F, bits, syn_out,
                                           static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+static bool valid_dim(int d) { return d == 1 || d == 2 || d == 4 || d == 8; }
+
+int ldpc_reconciliation_llr(int32_t d, int32_t F, int32_t n, const float *x, const float *m,
+                            float sigma2, float *llr_out, void *stream) {
+    if (!valid_dim(d)) return fail_with(LDPC_EINVAL, "d = %d is not 1, 2, 4 or 8", d);
+    if (F < 1 || F > 65535 || n < 1) return fail_with(LDPC_EINVAL, "F = %d, n = %d", F, n);
+    if ((int64_t)n + d >= (1ll << 31)) return fail_with(LDPC_EINVAL, "n too large");
+    if (!(sigma2 > 0.0f)) return fail_with(LDPC_EINVAL, "sigma2 must be > 0");
+    if (!x || !m || !llr_out) return fail_with(LDPC_EINVAL, "null pointer");
+    hipError_t e = ldpc::enqueue_reconciliation_llr(d, F, n, x, m, sigma2, llr_out,
+                                                    static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+int ldpc_reconciliation_message(int32_t d, int32_t F, int32_t n, const uint8_t *bits,
+                                const float *y, float *m_out, void *stream) {
+    if (!valid_dim(d)) return fail_with(LDPC_EINVAL, "d = %d is not 1, 2, 4 or 8", d);
+    if (F < 1 || F > 65535 || n < 1) return fail_with(LDPC_EINVAL, "F = %d, n = %d", F, n);
+    if ((int64_t)n + d >= (1ll << 31)) return fail_with(LDPC_EINVAL, "n too large");
+    if (!bits || !y || !m_out) return fail_with(LDPC_EINVAL, "null pointer");
+    hipError_t e = ldpc::enqueue_reconciliation_message(d, F, n, bits, y, m_out,
+                                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
     return LDPC_OK;
 }

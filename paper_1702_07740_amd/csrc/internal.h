@@ -21,9 +21,9 @@ namespace ldpc {
 enum : int32_t { KIND_STATE = 0, KIND_DEG1 = 1 };
 enum : int32_t { COL_CORE = 0, COL_DEG1 = 1, COL_DEG0 = 2 };
 
-// Check rows up to this degree share one kernel; larger rows (up to
-// LDPC_MAX_ROW_DEGREE) get their own, so their register needs do not lower
-// the occupancy of the common low-degree rows.
+// Check rows up to this degree with at most one degree-1 block share one
+// kernel; every other row (up to LDPC_MAX_ROW_DEGREE) goes to a generic one,
+// so their register needs do not lower the occupancy of the common rows.
 constexpr int kSmallRowDegree = 6;
 
 // Device view of a code: sizes plus pointers into small device tables.  Passed
@@ -39,8 +39,8 @@ struct CodeDev {
     // the first row_ns[r] are blocks of columns of degree >= 2 (stored
     // messages), the rest degree-1 blocks, each group in column order
     const int32_t *row_first, *row_deg, *row_ns;
-    // base rows ordered by degree class: the n_small rows of degree
-    // <= kSmallRowDegree first, then the n_large others
+    // base rows ordered by class: the n_small common rows (degree
+    // <= kSmallRowDegree, at most one degree-1 block) first, then the n_large others
     const int32_t *row_list;
     int32_t n_small, n_large;
     // per block: shift, kind, ref (state index or degree-1 index), column,
@@ -88,5 +88,9 @@ struct DecodeLaunch {
 hipError_t enqueue_decode(const DecodeLaunch &l);
 hipError_t enqueue_syndrome(const CodeDev &c, int F, const uint8_t *bits, uint8_t *syn,
                             hipStream_t stream);
+hipError_t enqueue_reconciliation_llr(int d, int F, int n, const float *x, const float *m,
+                                      float sigma2, float *llr, hipStream_t stream);
+hipError_t enqueue_reconciliation_message(int d, int F, int n, const uint8_t *bits, const float *y,
+                                          float *m, hipStream_t stream);
 
 }  // namespace ldpc

@@ -26,7 +26,7 @@ MAX_ROW_DEGREE = 16
 EXPORTS = (
     "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_info", "ldpc_decode_opts_init",
     "ldpc_workspace_bytes", "ldpc_decode_batch", "ldpc_syndrome", "ldpc_status_string",
-    "ldpc_last_error",
+    "ldpc_last_error", "ldpc_reconciliation_llr", "ldpc_reconciliation_message",
 )
 
 
@@ -89,6 +89,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.ldpc_status_string.argtypes = [ctypes.c_int]
         lib.ldpc_last_error.restype = ctypes.c_char_p
         lib.ldpc_last_error.argtypes = []
+        lib.ldpc_reconciliation_llr.restype = ctypes.c_int
+        lib.ldpc_reconciliation_llr.argtypes = [I32, I32, I32, P, P, ctypes.c_float, P, P]
+        lib.ldpc_reconciliation_message.restype = ctypes.c_int
+        lib.ldpc_reconciliation_message.argtypes = [I32, I32, I32, P, P, P, P]
         _lib = lib
         return lib
 
@@ -216,3 +220,39 @@ class Code:
                                   _stream_handle(stream))
         _check(st, "ldpc_syndrome")
         return syn
+
+
+def padded_length(n: int, d: int) -> int:
+    """Samples per frame of d-dimensional reconciliation: d * ceil(n / d)."""
+    return d * ((n + d - 1) // d)
+
+
+def reconciliation_llr(x, m, n: int, sigma2: float, d: int = 8, out=None, stream=None):
+    """Channel LLRs [F][n] from Alice's samples x and Bob's message m ([F][n_d] float32)."""
+    import torch
+    if x.dtype != torch.float32 or m.dtype != torch.float32 or x.shape != m.shape or x.dim() != 2:
+        raise ValueError("x and m must be float32 device tensors of one shape [F][n_d]")
+    if x.shape[1] != padded_length(n, d):
+        raise ValueError("frames must hold d * ceil(n / d) samples")
+    x, m = x.contiguous(), m.contiguous()
+    if out is None:
+        out = torch.empty((x.shape[0], n), dtype=torch.float32, device=x.device)
+    st = load().ldpc_reconciliation_llr(d, x.shape[0], n, x.data_ptr(), m.data_ptr(),
+                                        float(sigma2), out.data_ptr(), _stream_handle(stream))
+    _check(st, "ldpc_reconciliation_llr")
+    return out
+
+
+def reconciliation_message(bits, y, d: int = 8, out=None, stream=None):
+    """Bob's message M = U Y per d-tuple from key bits [F][n] and samples y [F][n_d]."""
+    import torch
+    F, n = bits.shape
+    if bits.dtype != torch.uint8 or y.dtype != torch.float32 or y.shape != (F, padded_length(n, d)):
+        raise ValueError("bits uint8 [F][n] and y float32 [F][d*ceil(n/d)] expected")
+    bits, y = bits.contiguous(), y.contiguous()
+    if out is None:
+        out = torch.empty_like(y)
+    st = load().ldpc_reconciliation_message(d, F, n, bits.data_ptr(), y.data_ptr(), out.data_ptr(),
+                                            _stream_handle(stream))
+    _check(st, "ldpc_reconciliation_message")
+    return out

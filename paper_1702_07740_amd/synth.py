@@ -97,22 +97,23 @@ def noiseless_llr(x: np.ndarray, magnitude: float = 20.0) -> np.ndarray:
     return (magnitude * (1.0 - 2.0 * x.astype(np.float64))).astype(np.float32)
 
 
-def gaussian_8d(n: int, F: int, snr_db: float, seed: int, first_frame: int = 0):
-    """Inputs of the 8-dimensional reconciliation front-end (Sec. II-C.3).
+def reconciliation_inputs(n: int, d: int, F: int, snr_db: float, seed: int, first_frame: int = 0):
+    """Inputs of d-dimensional reverse reconciliation (Sec. II-C.3).
 
-    Returns (c, X, Z) with key bits c uint8 [F][n], Alice's Gaussian samples
-    X ~ N(0, 1) and channel noise Z ~ N(0, sigma^2), both float64 [F][n8],
-    where n8 = 8 * ceil(n / 8): the last tuple is padded with extra samples
-    and its padding coordinates are dropped after the LLRs are formed.
+    Returns (c, X, Z): key bits c uint8 [F][n], Alice's Gaussian samples
+    X ~ N(0, 1) and channel noise Z ~ N(0, sigma^2), both float64 [F][n_d]
+    with n_d = d * ceil(n / d); the last tuple is padded with extra samples
+    whose coordinates are dropped after the LLRs are formed.  Bob holds
+    Y = X + Z.
     """
     sigma = math.sqrt(sigma2_from_snr_db(snr_db))
-    n8 = 8 * ((n + 7) // 8)
+    nd = d * ((n + d - 1) // d)
     c = np.empty((F, n), dtype=np.uint8)
-    X = np.empty((F, n8), dtype=np.float64)
-    Zn = np.empty((F, n8), dtype=np.float64)
+    X = np.empty((F, nd), dtype=np.float64)
+    Zn = np.empty((F, nd), dtype=np.float64)
     for f in range(F):
-        rng = np.random.default_rng([0x0C7A, seed, first_frame + f])
+        rng = np.random.default_rng([0x0C7A, d, seed, first_frame + f])
         c[f] = rng.integers(0, 2, size=n, dtype=np.uint8)
-        X[f] = rng.standard_normal(n8)
-        Zn[f] = sigma * rng.standard_normal(n8)
+        X[f] = rng.standard_normal(nd)
+        Zn[f] = sigma * rng.standard_normal(nd)
     return c, X, Zn

@@ -366,3 +366,26 @@ def test_single_check_update_accuracy_over_the_phi_range(ldpc, oracle_mod, D):
     err = np.abs(L.astype(np.float64) - L_r)
     bound = 1e-5 * np.maximum(np.abs(L_r), np.abs(m_r)) + 1e-30
     assert np.all(err <= bound), float(np.max(err / bound))
+
+
+def test_rows_with_several_degree_1_blocks(ldpc, oracle_mod):
+    """Checks joined to two degree-1 variables, and a check joined only to
+    degree-1 variables, take the generic row path."""
+    rng = np.random.default_rng(9)
+    Z = 45
+    base = np.full((4, 10), -1, dtype=np.int32)
+    base[0, [0, 1, 2]] = rng.integers(0, Z, 3)
+    base[1, [0, 1, 2, 3]] = rng.integers(0, Z, 4)      # column 3 has degree 1
+    base[2, [0, 4, 5]] = rng.integers(0, Z, 3)         # columns 4, 5 have degree 1
+    base[3, [6, 7]] = rng.integers(0, Z, 2)            # only degree-1 columns
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x, Q = synth.biawgn_frames(o.n, 3, 1.0, seed=19)
+    s = o.syndrome(x)
+    _say("several degree-1 blocks per row")
+    for T in (1, 3, 8):
+        bits, it, conv, L = _gpu_decode(g, Q, s, T, early_stop=False, want_llr=True)
+        _, L_r, _, _ = o.decode(Q, s, T, early_stop=False)
+        ok, worst, _ = llr_close(L, L_r)
+        assert ok, worst
+    bits, it, conv, L = _gpu_decode(g, Q, s, 30)
+    check_decode_parity(o, Q, s, bits, it, conv, o.decode(Q, s, 30), 30)
