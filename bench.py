@@ -32,6 +32,35 @@ METRIC = "raw decoded Mbit/s, n=1e6 R=0.02, 100 iters; p99 latency; FP16 vs FP32
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 PAPER_KRAW_MBPS = 1.72       # GTX 1080, q=21 QC code, Table II (context only)
 
+# HBM traffic of the steady check pass per launch (8 frames of this workload),
+# from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
+# each scaled by what the counter reads for a 1 GiB device copy
+# (FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB: factors 2.0 and 1.0).  It holds
+# only for the kernel sources it was taken on; any change to them makes the
+# fingerprint differ and the figure is reported as null.
+KERNEL_SOURCES = ("internal.h", "passes.h", "decoder.hip")
+MEASURED_TRAFFIC = {
+    "check_pass": {"sources": "4d2d3a67a15beeed", "fetch_kib": 55618.5, "write_kib": 65388.4,
+                   "fetch_scale": 2.0, "write_scale": 1.0},
+}
+
+
+def kernel_fingerprint() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1702_07740_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the counters, or None if stale."""
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None or m["sources"] != kernel_fingerprint():
+        return None
+    return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+
 
 class HipEvents:
     """hipEvent_t handles through the HIP runtime torch already loaded."""
@@ -123,9 +152,11 @@ def kernel_roofline(torch, code, dQ, ds, T, steps, F, info):
     vn_gbs = float(np.sum(vn_bytes * active_vn) / (np.sum(vn_ms) * 1e-3) / 1e9)
     return {
         "check_pass": {"avg_ms": float(np.mean(cn_ms)), "achieved_GBs": cn_gbs,
-                       "bytes_per_frame": float(cn_bytes[-1]), "share": float(np.sum(cn_ms) / (np.sum(cn_ms) + np.sum(vn_ms)))},
+                       "bytes_per_frame": float(cn_bytes[-1]),
+                       "bytes_per_launch": float(cn_bytes[-1]) * F, "share": float(np.sum(cn_ms) / (np.sum(cn_ms) + np.sum(vn_ms)))},
         "variable_pass": {"avg_ms": float(np.mean(vn_ms)), "achieved_GBs": vn_gbs,
-                          "bytes_per_frame": float(vn_bytes[-1]), "share": float(np.sum(vn_ms) / (np.sum(cn_ms) + np.sum(vn_ms)))},
+                          "bytes_per_frame": float(vn_bytes[-1]),
+                          "bytes_per_launch": float(vn_bytes[-1]) * F, "share": float(np.sum(vn_ms) / (np.sum(cn_ms) + np.sum(vn_ms)))},
     }
 
 
@@ -147,6 +178,167 @@ def cpu_baseline(base, Z, n, snr, seed, threads, iters_sample):
                       f"{wall:.1f} s wall on {threads} threads, scaled to 100 iterations"}
 
 
+def wilson(k, n, z=1.959964):
+    if n == 0:
+        return (0.0, 1.0)
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * np.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / d
+    return (float(max(0.0, c - h)), float(min(1.0, c + h)))
+
+
+def workload_mixed(torch, ldpc, args):
+    """64 frames over the 9 codes R in {0.02, 0.05, 0.1} x Z in {2048, 4096, 6667}
+    (frame f decodes with code f mod 9), each at its BP threshold + 0.3 dB, max 100
+    iterations: one engine run (all codes batched per iteration) against the plain
+    FP32 path (one ldpc_decode_batch per code, in sequence)."""
+    from paper_1702_07740_amd import serve, synth
+    thr = serve.template_thresholds()
+    combos = [(R, Z) for R in (0.02, 0.05, 0.1) for Z in (2048, 4096, 6667)]
+    counts = [len(range(i, 64, 9)) for i in range(9)]
+    groups = []
+    for (R, Z), F in zip(combos, counts):
+        code = ldpc.Code(synth.template_for_rate(R, Z, seed=1), Z)
+        snr = thr[R] + 0.3
+        x, Q = synth.biawgn_frames(code.n, F, snr, seed=3000 + Z + int(R * 1000))
+        dx = torch.from_numpy(x).cuda()
+        groups.append((R, Z, F, snr, code, torch.from_numpy(Q).cuda(), code.syndrome(dx), x))
+    torch.cuda.synchronize()
+    T = args.max_iters
+    total_bits = sum(g[2] * g[4].n for g in groups)
+
+    def plain(fp16=False):
+        outs = []
+        for R, Z, F, snr, code, Q, s, x in groups:
+            outs.append(code.decode(Q, s, T, msg_fp16=fp16))
+        return outs
+
+    from paper_1702_07740_amd import autotune
+    reqs = [(code, Q, s) for R, Z, F, snr, code, Q, s, x in groups]
+    cpt32, tune32 = autotune.tune_engine(reqs, msg_fp16=False, use_cache=False)
+    cpt16, tune16 = autotune.tune_engine(reqs, msg_fp16=True, use_cache=False)
+
+    def engine(fp16=False):
+        eng = ldpc.Engine(64 << 30, max_slots=16, msg_fp16=fp16,
+                          checks_per_thread=cpt16 if fp16 else cpt32)
+        tickets = [eng.submit(code, Q, s, T) for R, Z, F, snr, code, Q, s, x in groups]
+        res = eng.drain(tickets)
+        eng.close()
+        return [res[t] for t in tickets]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+
+    reps = max(1, min(args.steps, 5))
+    t_plain, o_plain = timed(lambda: plain(False), reps)
+    t_eng, o_eng = timed(lambda: engine(False), reps)
+    t_eng16, o_eng16 = timed(lambda: engine(True), reps)
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(o_plain, o_eng))
+    fer = {}
+    for name, outs in (("plain_fp32", o_plain), ("engine_fp32", o_eng), ("engine_fp16", o_eng16)):
+        errs = sum(int(np.sum(np.any(o[0].cpu().numpy() != g[7], axis=1))) for o, g in zip(outs, groups))
+        fer[name] = {"frame_errors": errs, "frames": 64, "fer": errs / 64, "ci95": wilson(errs, 64)}
+    return {
+        "metric": "raw decoded Mbit/s, 64 mixed frames (R 0.02/0.05/0.1 x Z 2048/4096/6667)",
+        "value": round(total_bits / t_eng / 1e6, 3), "unit": "Mbit/s", "n_gpus": 1,
+        "steps": reps, "warmup": 1, "ms_per_step": round(t_eng * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mixed codes in one engine batch, threshold + 0.3 dB, max "
+                               f"{T} iterations", "codes": [[R, Z, F, round(snr, 3)] for R, Z, F, snr, *_ in groups]},
+        "plain_fp32_mbit_s": round(total_bits / t_plain / 1e6, 3),
+        "engine_fp16_mbit_s": round(total_bits / t_eng16 / 1e6, 3),
+        "engine_equals_plain_bitwise": bool(same), "fer": fer,
+        "autotune": {"fp32": {"checks_per_thread": cpt32, "ms": tune32},
+                     "fp16": {"checks_per_thread": cpt16, "ms": tune16}},
+    }
+
+
+def workload_frontend(torch, ldpc, args):
+    """8-D reconciliation: Bob's message and Alice's LLRs on the device (octonion
+    products), then FP16-message decoding of the n = 1,000,050 code; 8 frames."""
+    from paper_1702_07740_amd import synth
+    Z, F, T, d = 6667, args.frames, args.max_iters, 8
+    code = ldpc.Code(synth.template_base(144, Z, seed=1), Z)
+    sigma2 = synth.sigma2_from_snr_db(args.snr)
+    c, X, Zn = synth.reconciliation_inputs(code.n, d, F, args.snr, seed=44)
+    dc = torch.from_numpy(c).cuda()
+    dX = torch.from_numpy(X.astype(np.float32)).cuda()
+    dY = torch.from_numpy((X + Zn).astype(np.float32)).cuda()
+    s = code.syndrome(dc)
+    M = ldpc.reconciliation_message(dc, dY, d=d)
+    ws = code.alloc_workspace(F, T, msg_fp16=True)
+    L = torch.empty((F, code.n), dtype=torch.float32, device="cuda")
+
+    def step():
+        ldpc.reconciliation_llr(dX, M, code.n, sigma2, d=d, out=L)
+        return code.decode(L, s, T, msg_fp16=True, workspace=ws)
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        out = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    errs = int(np.sum(np.any(out[0].cpu().numpy() != c, axis=1)))
+    return {
+        "metric": "raw decoded Mbit/s, 8-D reconciliation front-end + FP16 decode, n=1,000,050",
+        "value": round(F * code.n / (ms * 1e-3) / 1e6, 3), "unit": "Mbit/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"d=8 reconciliation, {F} frames at {args.snr} dB, FP16 messages, "
+                               f"max {T} iterations", "n": code.n, "Z": Z, "frames": F},
+        "fer": errs / F, "avg_iters": float(out[1].float().mean().item()),
+    }
+
+
+def workload_serving(torch, ldpc, args):
+    """Poisson requests of mixed codes through the engine (continuous batching,
+    admission by HBM budget) against the plain FP32 one-at-a-time path on the same
+    trace."""
+    import copy
+    from paper_1702_07740_amd import serve
+    pools = serve.make_pools(ldpc, torch)
+    # capacity probe: a saturating burst through the engine
+    burst = serve.poisson_trace(len(pools), 1e6, 64 / 1e6 + 1e-9, seed=1)[:64]
+    for r in burst:
+        r.arrival = 0.0
+    st, _ = serve.run_engine(ldpc, torch, pools, copy.deepcopy(burst), 200 << 30)
+    cap = st["requests"] / st["wall_s"]
+    lam = args.serve_load * cap
+    trace = serve.poisson_trace(len(pools), lam, args.duration, seed=11)
+    print(f"[bench] serving: capacity {cap:.1f} req/s, {len(trace)} requests", file=sys.stderr,
+          flush=True)
+    eng, _ = serve.run_engine(ldpc, torch, pools, copy.deepcopy(trace), 200 << 30)
+    print(f"[bench] serving: engine {eng}", file=sys.stderr, flush=True)
+    small, _ = serve.run_engine(ldpc, torch, pools, copy.deepcopy(trace), 256 << 20)
+    print(f"[bench] serving: engine, 256 MB budget {small}", file=sys.stderr, flush=True)
+    one, _ = serve.run_one_at_a_time(ldpc, torch, pools, copy.deepcopy(trace))
+    print(f"[bench] serving: one at a time {one}", file=sys.stderr, flush=True)
+    return {
+        "metric": "serving: raw decoded Mbit/s and p50/p99 latency, Poisson mixed-code requests",
+        "value": round(eng["mbit_s"], 3), "unit": "Mbit/s", "n_gpus": 1, "steps": len(trace),
+        "warmup": 0, "ms_per_step": eng["mean_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Poisson arrivals at {lam:.1f} req/s ({args.serve_load:.0%} of "
+                               f"measured capacity {cap:.1f} req/s) for {args.duration} s; R in "
+                               "{0.02,0.05,0.1}, Z in {1024,2048,4096,6667}, 1-4 frames, "
+                               "threshold + 0.3 dB, max 100 iterations",
+                   "budget_bytes": 200 << 30},
+        "latency_ms": {"p50": eng["p50_ms"], "p99": eng["p99_ms"]},
+        "engine": eng, "engine_256MB_budget": small, "one_at_a_time_fp32": one,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +350,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--workload", default="decode",
+                    choices=["decode", "mixed", "frontend", "serving"],
+                    help="decode: the n=1,000,050 headline; mixed: 64 frames of 9 codes in one "
+                         "engine batch; frontend: 8-D reconciliation + FP16 decode; serving: "
+                         "Poisson requests through the engine")
+    ap.add_argument("--duration", type=float, default=60.0, help="serving run length (s)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="serving arrival rate as a fraction of measured capacity")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 3 times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -179,6 +379,12 @@ def main():
 
     import torch
     from paper_1702_07740_amd import ldpc, synth
+
+    if args.workload != "decode":
+        fn = {"mixed": workload_mixed, "frontend": workload_frontend,
+              "serving": workload_serving}[args.workload]
+        print(json.dumps(fn(torch, ldpc, args)), flush=True)
+        return
 
     Z, F, T = 6667, args.frames, args.max_iters
     base = synth.template_base(144, Z, seed=1)
@@ -235,12 +441,14 @@ def main():
         res["roofline"] = {"bound": "hbm", "kernel": dom,
                            "achieved": round(kr[dom]["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(kr[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                           "traffic": None, "avg_ms": kr[dom]["avg_ms"], "kernels": kr}
+                           "traffic": measured_traffic(dom),
+                           "algorithmic_bytes": kr[dom]["bytes_per_launch"],
+                           "avg_ms": kr[dom]["avg_ms"], "kernels": kr}
         print("[bench] roofline done", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
-        res["cpu_baseline"] = cpu_baseline(base, Z, n, args.snr, 2026, threads, 4)
+        res["cpu_baseline"] = cpu_baseline(base, Z, n, args.snr, 2026, threads, 8)
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
 
     print(json.dumps(res), flush=True)

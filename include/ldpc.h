@@ -96,7 +96,11 @@ typedef struct {
                                 t = 0, i.e. also on the channel decisions            */
     int32_t msg_fp16;        /* 1: check-to-variable messages stored as IEEE half;
                                 all arithmetic and sums stay in float32             */
-    int32_t reserved;        /* must be 0                                          */
+    int32_t checks_per_thread; /* schedule of the check kernel: checks of one base
+                                row per thread, 1, 2 or 4 (0 = library default 4);
+                                a block row's Z checks take ceil(Z / (256 *
+                                checks_per_thread)) workgroups.  Results do not
+                                depend on it                                      */
     float *llr_out;          /* optional device [F][n]: posterior L_v at exit      */
     void **timing_events;    /* optional host array of caller-created hipEvent_t
                                 handles, recorded on the decode stream around the
@@ -107,7 +111,7 @@ typedef struct {
 } ldpc_decode_opts;
 
 /* Fill opts with the defaults {early_stop=1, check_from_iter=0, msg_fp16=0,
- * reserved=0, llr_out=NULL, timing_events=NULL, n_timing_events=0}. */
+ * checks_per_thread=0, llr_out=NULL, timing_events=NULL, n_timing_events=0}. */
 void ldpc_decode_opts_init(ldpc_decode_opts *opts);
 
 /* Workspace bytes ldpc_decode_batch needs for F frames and max_iters iterations
@@ -133,7 +137,7 @@ size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
  * independent: frame f's outputs depend only on frame f's inputs, bit for bit,
  * whatever F and the other frames are.
  * Errors: LDPC_EINVAL (F < 1, max_iters < 0, check_from_iter < 0, null
- * pointer, reserved != 0, too few timing events), LDPC_EWORKSPACE, LDPC_EDEVICE (current device is
+ * pointer, checks_per_thread not 0/1/2/4, too few timing events), LDPC_EWORKSPACE, LDPC_EDEVICE (current device is
  * not the code's device, or a launch failed).
  */
 int ldpc_decode_batch(const ldpc_code *code, int32_t F,
@@ -181,6 +185,73 @@ int ldpc_reconciliation_llr(int32_t d, int32_t F, int32_t n, const float *x, con
  */
 int ldpc_reconciliation_message(int32_t d, int32_t F, int32_t n, const uint8_t *bits,
                                 const float *y, float *m_out, void *stream);
+
+/*
+ * Multi-request engine: iteration-level scheduling of decode requests of mixed
+ * codes on one GPU stream (continuous batching).  Each engine step runs one
+ * flooding iteration (Alg. 1, Steps 2-4) of every admitted request in a single
+ * check launch and a single variable launch that cover all of them; a request
+ * submitted while others decode is admitted at the next step once a slot is
+ * free and its decode state fits the HBM budget, and leaves as soon as all its
+ * frames have stopped (or after its last iteration).  Per frame the engine runs
+ * exactly the kernels of ldpc_decode_batch in the same order, so every request's
+ * outputs are bit-identical to decoding it alone with the same options.
+ *
+ * The engine owns its device memory: a cap of hbm_budget_bytes on the state of
+ * admitted requests, taken from the device in chunks of up to 1 GiB when first
+ * needed and kept until ldpc_engine_destroy.  Calls on one engine must not run
+ * concurrently.  Supported codes: every base row of degree <= 6 with at most one
+ * degree-1 block (the multi-edge families); others give LDPC_EUNSUPPORTED.
+ */
+typedef struct ldpc_engine ldpc_engine;
+
+typedef struct {
+    size_t hbm_budget_bytes; /* most device bytes of decode state admitted at once   */
+    int32_t max_slots;       /* most requests in flight, 1..64                        */
+    int32_t msg_fp16;        /* 1: messages stored as IEEE half (as ldpc_decode_opts)  */
+    int32_t early_stop;      /* as ldpc_decode_opts.early_stop                         */
+    int32_t checks_per_thread; /* check-kernel schedule as in ldpc_decode_opts      */
+    void *stream;            /* hipStream_t for all engine work; NULL = null stream    */
+} ldpc_engine_config;
+
+/* Create an engine on the current device.  Errors: LDPC_EINVAL (null, budget 0,
+ * max_slots outside 1..64, checks_per_thread not 0/1/2/4), LDPC_ENOMEM, LDPC_EDEVICE. */
+int ldpc_engine_create(const ldpc_engine_config *cfg, ldpc_engine **out);
+
+/* Wait for the engine's stream, free its memory; queued requests are dropped.
+ * NULL is ignored. */
+void ldpc_engine_destroy(ldpc_engine *engine);
+
+/* Device bytes of decode state one request takes from the budget. */
+size_t ldpc_engine_request_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
+                                 int32_t msg_fp16);
+
+/*
+ * Queue a request of F frames (pointers as in ldpc_decode_batch; device
+ * buffers owned by the caller, which must keep them, and the code, alive until
+ * the ticket is reported by ldpc_engine_poll).  Nothing is launched here.
+ *   ticket_out  host; receives an id > 0 that ldpc_engine_poll reports when the
+ *               request's outputs are written
+ * Errors: LDPC_EINVAL (argument, or a request larger than the whole budget),
+ * LDPC_EUNSUPPORTED (code shape), LDPC_EDEVICE (code on another device).
+ */
+int ldpc_engine_submit(ldpc_engine *engine, const ldpc_code *code, int32_t F, const float *llr,
+                       const uint8_t *syndrome, int32_t max_iters, uint8_t *bits_out,
+                       int32_t *iters_out, uint8_t *converged_out, int64_t *ticket_out);
+
+/*
+ * One engine step on the engine's stream: retire requests whose frames have all
+ * stopped (read-out enqueued), admit queued requests in arrival order while a slot
+ * and budget are free, then one iteration of every active request.  Asynchronous.
+ *   active_out, queued_out  host, nullable: requests in flight / still queued
+ * Errors: LDPC_EDEVICE.
+ */
+int ldpc_engine_step(ldpc_engine *engine, int32_t *active_out, int32_t *queued_out);
+
+/* Report up to `capacity` tickets whose outputs are complete (each once).
+ *   tickets_out host [capacity]; count_out host.  Errors: LDPC_EINVAL. */
+int ldpc_engine_poll(ldpc_engine *engine, int64_t *tickets_out, int32_t capacity,
+                     int32_t *count_out);
 
 /* Static English text for a status code. */
 const char *ldpc_status_string(int status);

@@ -1,6 +1,7 @@
 // C ABI of libldpc.so (declared in include/ldpc.h): argument checking, code
 // tables, workspace sizing, and the enqueue of the decoder kernels.
 #include "../../include/ldpc.h"
+#include "engine.h"
 #include "internal.h"
 
 #include <cstdarg>
@@ -8,6 +9,7 @@
 #include <new>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 using ldpc::CodeDev;
@@ -67,7 +69,7 @@ void ldpc_decode_opts_init(ldpc_decode_opts *o) {
     o->early_stop = 1;
     o->check_from_iter = 0;
     o->msg_fp16 = 0;
-    o->reserved = 0;
+    o->checks_per_thread = 0;
     o->llr_out = nullptr;
     o->timing_events = nullptr;
     o->n_timing_events = 0;
@@ -232,6 +234,8 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.row_deg = T + o_row_deg;
     d.row_ns = T + o_row_ns;
     d.row_list = T + o_rl;
+    d.max_core_deg = 0;
+    for (int k = 0; k < NC; ++k) d.max_core_deg = std::max(d.max_core_deg, core_deg[k]);
     d.n_small = n_small;
     d.n_large = mb - n_small;
     d.blk_shift = T + o_bs;
@@ -299,7 +303,10 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const 
     ldpc_decode_opts o;
     ldpc_decode_opts_init(&o);
     if (opts) o = *opts;
-    if (o.reserved != 0) return fail_with(LDPC_EINVAL, "opts.reserved must be 0");
+    const int cpt = o.checks_per_thread == 0 ? ldpc::kDefaultChecksPerThread : o.checks_per_thread;
+    if (cpt != 1 && cpt != 2 && cpt != 4)
+        return fail_with(LDPC_EINVAL, "checks_per_thread = %d is not 0, 1, 2 or 4",
+                         o.checks_per_thread);
     if (o.check_from_iter < 0) return fail_with(LDPC_EINVAL, "check_from_iter < 0");
     if (o.timing_events && o.n_timing_events < 2 * max_iters + 1)
         return fail_with(LDPC_EINVAL, "%d timing events; need 2*max_iters + 1 = %d",
@@ -321,6 +328,7 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const 
     l.early_stop = o.early_stop ? 1 : 0;
     l.check_from = o.check_from_iter;
     l.fp16 = o.msg_fp16 ? 1 : 0;
+    l.cpt = cpt;
     l.llr = llr;
     l.syndrome = syndrome;
     l.bits_out = bits_out;
@@ -372,6 +380,104 @@ int ldpc_reconciliation_message(int32_t d, int32_t F, int32_t n, const uint8_t *
     hipError_t e = ldpc::enqueue_reconciliation_message(d, F, n, bits, y, m_out,
                                                         static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+struct ldpc_engine {
+    ldpc::Engine e;
+};
+
+int ldpc_engine_create(const ldpc_engine_config *cfg, ldpc_engine **out) {
+    if (!out) return fail_with(LDPC_EINVAL, "out is null");
+    *out = nullptr;
+    if (!cfg) return fail_with(LDPC_EINVAL, "cfg is null");
+    if (cfg->hbm_budget_bytes == 0) return fail_with(LDPC_EINVAL, "hbm_budget_bytes is 0");
+    if (cfg->max_slots < 1 || cfg->max_slots > ldpc::kEngineMaxSlots)
+        return fail_with(LDPC_EINVAL, "max_slots = %d outside 1..%d", cfg->max_slots,
+                         ldpc::kEngineMaxSlots);
+    const int cpt = cfg->checks_per_thread == 0 ? ldpc::kDefaultChecksPerThread : cfg->checks_per_thread;
+    if (cpt != 1 && cpt != 2 && cpt != 4)
+        return fail_with(LDPC_EINVAL, "checks_per_thread = %d is not 0, 1, 2 or 4",
+                         cfg->checks_per_thread);
+    ldpc_engine *en = new (std::nothrow) ldpc_engine();
+    if (!en) return fail_with(LDPC_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&en->e.device);
+    if (e == hipSuccess)
+        e = en->e.init(cfg->hbm_budget_bytes, cfg->max_slots, cfg->msg_fp16 != 0,
+                       cfg->early_stop != 0, cpt, cfg->stream);
+    if (e != hipSuccess) {
+        en->e.destroy();
+        delete en;
+        return fail_with(e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EDEVICE, "engine: %s",
+                         hipGetErrorString(e));
+    }
+    *out = en;
+    return LDPC_OK;
+}
+
+void ldpc_engine_destroy(ldpc_engine *en) {
+    if (!en) return;
+    en->e.destroy();
+    delete en;
+}
+
+size_t ldpc_engine_request_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
+                                 int32_t msg_fp16) {
+    if (!code || F < 1 || max_iters < 0) return 0;
+    return ldpc::Engine::request_bytes(code->dev, F, max_iters, msg_fp16 != 0);
+}
+
+int ldpc_engine_submit(ldpc_engine *en, const ldpc_code *code, int32_t F, const float *llr,
+                       const uint8_t *syndrome, int32_t max_iters, uint8_t *bits_out,
+                       int32_t *iters_out, uint8_t *converged_out, int64_t *ticket_out) {
+    if (!en || !code || !ticket_out) return fail_with(LDPC_EINVAL, "null engine, code or ticket");
+    if (F < 1 || F > 65535) return fail_with(LDPC_EINVAL, "F = %d outside [1, 65535]", F);
+    if (max_iters < 0) return fail_with(LDPC_EINVAL, "max_iters = %d < 0", max_iters);
+    if (!llr || !syndrome || !bits_out || !iters_out || !converged_out)
+        return fail_with(LDPC_EINVAL, "null input or output pointer");
+    if ((int64_t)(max_iters + 1) * F >= (1ll << 31))
+        return fail_with(LDPC_EINVAL, "(max_iters + 1) * F too large");
+    if (code->dev.n_large > 0)
+        return fail_with(LDPC_EUNSUPPORTED,
+                         "the engine takes codes whose rows have degree <= %d and at most one "
+                         "degree-1 block", ldpc::kSmallRowDegree);
+    if (code->device != en->e.device)
+        return fail_with(LDPC_EDEVICE, "code on device %d, engine on device %d", code->device,
+                         en->e.device);
+    const size_t need = ldpc::Engine::request_bytes(code->dev, F, max_iters, en->e.fp16);
+    if (need > en->e.budget_bytes)
+        return fail_with(LDPC_EINVAL, "request needs %zu bytes, budget is %zu", need,
+                         en->e.budget_bytes);
+    ldpc::Request r{};
+    r.c = code->dev;
+    r.F = F;
+    r.T = max_iters;
+    r.llr = llr;
+    r.syndrome = syndrome;
+    r.bits_out = bits_out;
+    r.iters_out = iters_out;
+    r.conv_out = converged_out;
+    *ticket_out = en->e.submit(r);
+    return LDPC_OK;
+}
+
+int ldpc_engine_step(ldpc_engine *en, int32_t *active_out, int32_t *queued_out) {
+    if (!en) return fail_with(LDPC_EINVAL, "engine is null");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != en->e.device)
+        return fail_with(LDPC_EDEVICE, "current device is not the engine's device");
+    int a = 0, q = 0;
+    hipError_t e = en->e.step(&a, &q);
+    if (active_out) *active_out = a;
+    if (queued_out) *queued_out = q;
+    if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "engine step: %s", hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+int ldpc_engine_poll(ldpc_engine *en, int64_t *tickets_out, int32_t capacity, int32_t *count_out) {
+    if (!en || !count_out || (capacity > 0 && !tickets_out))
+        return fail_with(LDPC_EINVAL, "null argument");
+    *count_out = capacity > 0 ? en->e.poll(tickets_out, capacity) : 0;
     return LDPC_OK;
 }
 

@@ -42,29 +42,54 @@ using namespace dev;
 
 // One launch covers the rows of one degree class; grid.y walks that class's
 // rows in the row list.
-template <typename Msg, bool kLarge, int MODE>
+template <typename Msg, bool kLarge, int MODE, int CPT>
 __global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A) {
     const int f = blockIdx.z;
     const int r = c.row_list[(kLarge ? c.n_small : 0) + (int)blockIdx.y];
     if (A.skip_after >= 0 && A.fail[(size_t)A.skip_after * A.F + f] == 0) return;
-    check_work<Msg, kLarge, MODE>(c, A, f, r, blockIdx.x);
+    check_work<Msg, kLarge, MODE, CPT>(c, A, f, r, blockIdx.x);
 }
 
+// Common rows run with the requested checks per thread (1, 2 or 4); the rare
+// generic rows always with the default.
 template <typename Msg, int MODE>
-void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, hipStream_t st) {
-    const unsigned tiles_a =
-        (unsigned)((c.Z + kBlock * kChecksPerThread - 1) / (kBlock * kChecksPerThread));
-    if (c.n_small > 0)
-        check_pass<Msg, false, MODE><<<dim3(tiles_a, c.n_small, F), dim3(kBlock), 0, st>>>(c, a);
+void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, int cpt, hipStream_t st) {
+    if (c.n_small > 0) {
+        const dim3 g(check_tiles(c.Z, cpt), c.n_small, F);
+        if (cpt == 1)
+            check_pass<Msg, false, MODE, 1><<<g, dim3(kBlock), 0, st>>>(c, a);
+        else if (cpt == 2)
+            check_pass<Msg, false, MODE, 2><<<g, dim3(kBlock), 0, st>>>(c, a);
+        else
+            check_pass<Msg, false, MODE, 4><<<g, dim3(kBlock), 0, st>>>(c, a);
+    }
     if (c.n_large > 0)
-        check_pass<Msg, true, MODE><<<dim3(tiles_a, c.n_large, F), dim3(kBlock), 0, st>>>(c, a);
+        check_pass<Msg, true, MODE, kDefaultChecksPerThread>
+            <<<dim3(check_tiles(c.Z, kDefaultChecksPerThread), c.n_large, F), dim3(kBlock), 0, st>>>(c, a);
 }
 
-template <typename Msg>
+template <int U, typename Msg>
 __global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A) {
     const int f = blockIdx.z;
     if (A.fail[(size_t)(A.t - 1) * A.F + f] == 0) return;
-    variable_work<Msg>(c, A, f, blockIdx.y, blockIdx.x);
+    variable_work<U, Msg>(c, A, f, blockIdx.y, blockIdx.x);
+}
+
+// Batch width of the variable pass: batches of about 20 loads (measured: wider
+// batches flood the memory pipeline, padded slots cost real loads), sized so
+// that they divide the column degree with little padding, e.g. 3 x 17 for 51.
+template <typename Msg>
+void launch_variable_pass(const CodeDev &c, const VnArgs &v, const dim3 &grid, hipStream_t st) {
+    const int u = variable_batch(c.max_core_deg);
+    const dim3 b(kBlock);
+    switch (u) {
+        case 8: variable_pass<8, Msg><<<grid, b, 0, st>>>(c, v); break;
+        case 11: variable_pass<11, Msg><<<grid, b, 0, st>>>(c, v); break;
+        case 16: variable_pass<16, Msg><<<grid, b, 0, st>>>(c, v); break;
+        case 17: variable_pass<17, Msg><<<grid, b, 0, st>>>(c, v); break;
+        case 21: variable_pass<21, Msg><<<grid, b, 0, st>>>(c, v); break;
+        default: variable_pass<26, Msg><<<grid, b, 0, st>>>(c, v); break;
+    }
 }
 
 // fail[t][f] = 1 marks "iteration t not checked or check failed".
@@ -90,6 +115,8 @@ __global__ __launch_bounds__(kBlock) void init_psi(CodeDev c, const float *llr, 
                                                    size_t psi_frame) {
     init_psi_work(c, llr, psi, psi_frame, blockIdx.z, blockIdx.y, blockIdx.x);
 }
+
+__global__ __launch_bounds__(64) void frame_exit(FinArgs A) { frame_exit_work(A, blockIdx.x); }
 
 __global__ __launch_bounds__(kBlock) void finalize(CodeDev c, FinArgs A) {
     finalize_work(c, A, blockIdx.y, blockIdx.x);
@@ -179,13 +206,13 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
         a.skip_after = t >= 2 ? t - 2 : -1;
         if (l.events) (void)hipEventRecord(l.events[2 * (t - 1)], st);
         if (t == 1)
-            launch_check_pass<Msg, kFirst>(c, a, F, st);
+            launch_check_pass<Msg, kFirst>(c, a, F, l.cpt, st);
         else
-            launch_check_pass<Msg, kSteady>(c, a, F, st);
+            launch_check_pass<Msg, kSteady>(c, a, F, l.cpt, st);
         if (l.events) (void)hipEventRecord(l.events[2 * (t - 1) + 1], st);
         if (c.NC > 0) {
             v.t = t;
-            variable_pass<Msg><<<vn_grid, dim3(kBlock), 0, st>>>(c, v);
+            launch_variable_pass<Msg>(c, v, vn_grid, st);
         }
     }
     if (l.events) (void)hipEventRecord(l.events[2 * T], st);
@@ -197,7 +224,7 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     a.d1_cur = nullptr;
     a.d1post = nullptr;
     a.skip_after = T >= 1 ? T - 1 : -1;
-    launch_check_pass<Msg, kVoteOnly>(c, a, F, st);
+    launch_check_pass<Msg, kVoteOnly>(c, a, F, l.cpt, st);
 
     FinArgs fa{};
     fa.llr = l.llr;
@@ -216,6 +243,7 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     fa.psi_frame = L.psi_frame;
     fa.F = F;
     fa.T = T;
+    frame_exit<<<dim3(F), dim3(64), 0, st>>>(fa);
     finalize<<<dim3(tiles(c.n), F), dim3(kBlock), 0, st>>>(c, fa);
     return hipGetLastError();
 }

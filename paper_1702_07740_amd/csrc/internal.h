@@ -26,6 +26,9 @@ enum : int32_t { COL_CORE = 0, COL_DEG1 = 1, COL_DEG0 = 2 };
 // so their register needs do not lower the occupancy of the common rows.
 constexpr int kSmallRowDegree = 6;
 
+// Default checks per thread of the common-row check kernel.
+constexpr int kDefaultChecksPerThread = 4;
+
 // Device view of a code: sizes plus pointers into small device tables.  Passed
 // by value as a kernel argument; every table index below is uniform across a
 // workgroup, so the loads are scalar.
@@ -50,6 +53,7 @@ struct CodeDev {
     // core_state[core_first[k] + i], core_shift[...], i < core_deg[k], in
     // increasing row order
     const int32_t *core_col, *core_first, *core_deg, *core_state, *core_shift;
+    int32_t max_core_deg;  // largest degree of a core column
     // per base column: kind and index within its kind
     const int32_t *col_kind, *col_ref;
     // per degree-1 column: its base column and the shift of its only block
@@ -72,6 +76,7 @@ struct DecodeLaunch {
     CodeDev c;
     int F, T;
     int early_stop, check_from, fp16;
+    int cpt;               // checks per thread of the common-row check kernel (1, 2, 4)
     const float *llr;
     const uint8_t *syndrome;
     uint8_t *bits_out;

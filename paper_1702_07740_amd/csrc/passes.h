@@ -147,10 +147,14 @@ __device__ __forceinline__ bool stored(const RowCtx<D, Msg> &R, int k) {
     else return k < R.ns;
 }
 
-// Checks per thread: a thread handles checks a, a + 256, a + 512, a + 768 of
-// one row, so the row's table reads are paid once and every thread has its
-// loads for several checks in flight together.
-constexpr int kChecksPerThread = 4;
+// Checks per thread (CPT): a thread handles checks a, a + 256, ..., a + 256 (CPT-1)
+// of one row, so the row's table reads are paid once and every thread has its
+// loads for several checks in flight together.  A row's Z checks take
+// ceil(Z / (256 CPT)) workgroups, i.e. 4 ceil(Z / (256 CPT)) wavefronts per
+// circulant block: the schedule knob the autotuner sets (1, 2 or 4).
+inline unsigned check_tiles(int Z, int cpt) {
+    return (unsigned)((Z + kBlock * cpt - 1) / (kBlock * cpt));
+}
 // how many of those are processed at once (bounded by registers for large D)
 template <int D> struct ChunkOf { static constexpr int value = D <= 4 ? 2 : 1; };
 
@@ -262,15 +266,15 @@ __device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs
     return bad;
 }
 
-template <int D, int DS, int MODE, typename Msg>
+template <int D, int DS, int MODE, typename Msg, int CPT>
 __device__ __forceinline__ void check_row(const CodeDev &c, const CnArgs &A, int f, int r,
                                           unsigned tile) {
     const RowCtx<D, Msg> R = load_row<D, Msg>(c, A, f, r);
-    constexpr int K = ChunkOf<D>::value;
-    const unsigned a0 = tile * (kBlock * kChecksPerThread) + threadIdx.x;
+    constexpr int K = ChunkOf<D>::value < CPT ? ChunkOf<D>::value : CPT;
+    const unsigned a0 = tile * (kBlock * CPT) + threadIdx.x;
     int bad = 0;
 #pragma unroll
-    for (int q0 = 0; q0 < kChecksPerThread; q0 += K)
+    for (int q0 = 0; q0 < CPT; q0 += K)
         bad |= check_chunk<D, DS, K, MODE, Msg>(R, A, a0 + q0 * kBlock);
     if (A.vote) {
         // One flag per frame and iteration, set by any workgroup holding an
@@ -290,13 +294,13 @@ __device__ __forceinline__ void check_row(const CodeDev &c, const CnArgs &A, int
 // most one degree-1 block, as in multi-edge codes) are compiled for every
 // (degree, stored blocks) pair; every other row goes to the generic class,
 // compiled per degree with the split read at run time.
-template <typename Msg, bool kLarge, int MODE>
+template <typename Msg, bool kLarge, int MODE, int CPT>
 __device__ __forceinline__ void check_work(const CodeDev &c, const CnArgs &A, int f, int r,
                                            unsigned tile) {
 #define LDPC_CASE(D) \
-    case D: check_row<D, -1, MODE, Msg>(c, A, f, r, tile); break;
+    case D: check_row<D, -1, MODE, Msg, CPT>(c, A, f, r, tile); break;
 #define LDPC_CASE2(D, S) \
-    case (D) * 32 + (S): check_row<D, S, MODE, Msg>(c, A, f, r, tile); break;
+    case (D) * 32 + (S): check_row<D, S, MODE, Msg, CPT>(c, A, f, r, tile); break;
     if (!kLarge) {
         static_assert(kSmallRowDegree == 6, "case list below covers degrees 1..6");
         switch (c.row_deg[r] * 32 + c.row_ns[r]) {
@@ -327,9 +331,22 @@ struct VnArgs {
     int F, t;
 };
 
+// Loads per batch of the variable pass for columns of degree <= max_deg: about
+// 20 per batch, rounded up to an instantiated width (8, 11, 16, 17, 21, 26).
+inline int variable_batch(int max_deg) {
+    const int nb = max_deg <= 0 ? 1 : (max_deg + 19) / 20;
+    const int u = (max_deg + nb - 1) / nb;
+    for (int w : {8, 11, 16, 17, 21, 26})
+        if (u <= w) return w;
+    return 26;
+}
+
 // Step 3 for the core columns: L_v = Q_v + sum of the column's messages, in
-// increasing row order.  One thread per (core column k, position j).
-template <typename Msg>
+// increasing row order.  One thread per (core column k, position j).  The
+// messages are loaded U at a time with all U loads in flight together (a
+// column of degree <= U takes one batch); slots past the column's degree load
+// a clamped in-range entry and add 0.
+template <int U, typename Msg>
 __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A, int f, int k,
                                               unsigned tile) {
     const unsigned Z = (unsigned)c.Z;
@@ -337,28 +354,21 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
     if (j >= Z) return;
     const Msg *msg = reinterpret_cast<const Msg *>(A.msg) + (size_t)f * A.msg_frame;
     const float *llr = A.llr + (size_t)f * c.n + (size_t)c.core_col[k] * Z;
-    float L = llr[j];
+    float L = at(llr, j);
     const int i0 = c.core_first[k], deg = c.core_deg[k];
-    // loads issued 16 at a time, sums kept in increasing row order
-    constexpr int U = 16;
-    int i = 0;
-    for (; i + U <= deg; i += U) {
+    for (int b = 0; b < deg; b += U) {
         float v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const unsigned s = (unsigned)c.core_shift[i0 + i + u];
+            const int i = i0 + min(b + u, deg - 1);
+            const unsigned s = (unsigned)c.core_shift[i];
             const unsigned idx = (j >= s) ? j - s : j + Z - s;
-            v[u] = msg_load<Msg>(msg + (unsigned)c.core_state[i0 + i + u] * Z + idx);
+            v[u] = msg_load<Msg>(&at(msg, (unsigned)c.core_state[i] * Z + idx));
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) L += v[u];
+        for (int u = 0; u < U; ++u) L += (b + u < deg) ? v[u] : 0.0f;
     }
-    for (; i < deg; ++i) {
-        const unsigned s = (unsigned)c.core_shift[i0 + i];
-        const unsigned idx = (j >= s) ? j - s : j + Z - s;
-        L += msg_load<Msg>(msg + (unsigned)c.core_state[i0 + i] * Z + idx);
-    }
-    A.tot[(size_t)f * A.tot_frame + (size_t)k * Z + j] = L;
+    at(A.tot + (size_t)f * A.tot_frame, (unsigned)k * Z + j) = L;
 }
 
 // Pack the syndrome bytes into 64-bit words per base row: bit a%64 of word a/64.
@@ -410,19 +420,33 @@ struct FinArgs {
     int F, T;
 };
 
-__device__ __forceinline__ void finalize_work(const CodeDev &c, const FinArgs &A, int f,
-                                              unsigned tile) {
+// Exit iteration and converged flag of frame f: the first checked iteration
+// whose parity check succeeded (fail flag 0), else max_iters and 0.  One
+// wave64 per frame scans 64 iterations per step with a ballot.
+__device__ __forceinline__ void frame_exit_work(const FinArgs &A, int f) {
+    const int lane = threadIdx.x & 63;
     int it = A.T, conv = 0;
-    for (int t = 0; t <= A.T; ++t)
-        if (A.fail[(size_t)t * A.F + f] == 0) {
-            it = t;
+    for (int t0 = 0; t0 <= A.T; t0 += 64) {
+        const int t = t0 + lane;
+        const bool ok = t <= A.T && A.fail[(size_t)t * A.F + f] == 0;
+        const unsigned long long m = wave_ballot(ok);
+        if (m) {
+            it = t0 + __builtin_ctzll(m);
             conv = 1;
             break;
         }
-    if (tile == 0 && threadIdx.x == 0) {
+    }
+    if (lane == 0) {
         A.iters_out[f] = it;
         A.conv_out[f] = (uint8_t)conv;
     }
+}
+
+// Read-out of frame f (after frame_exit_work): hard decisions and posteriors at
+// the exit iteration.
+__device__ __forceinline__ void finalize_work(const CodeDev &c, const FinArgs &A, int f,
+                                              unsigned tile) {
+    const int it = A.iters_out[f];
     const int v = tile * kBlock + threadIdx.x;
     if (v >= c.n) return;
     const int Z = c.Z;

@@ -27,6 +27,8 @@ EXPORTS = (
     "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_info", "ldpc_decode_opts_init",
     "ldpc_workspace_bytes", "ldpc_decode_batch", "ldpc_syndrome", "ldpc_status_string",
     "ldpc_last_error", "ldpc_reconciliation_llr", "ldpc_reconciliation_message",
+    "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_request_bytes", "ldpc_engine_submit",
+    "ldpc_engine_step", "ldpc_engine_poll",
 )
 
 
@@ -49,9 +51,17 @@ class CodeInfo(ctypes.Structure):
 class DecodeOpts(ctypes.Structure):
     _fields_ = [
         ("early_stop", ctypes.c_int32), ("check_from_iter", ctypes.c_int32),
-        ("msg_fp16", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("msg_fp16", ctypes.c_int32), ("checks_per_thread", ctypes.c_int32),
         ("llr_out", ctypes.c_void_p),
         ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
+    ]
+
+
+class EngineConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+        ("msg_fp16", ctypes.c_int32), ("early_stop", ctypes.c_int32),
+        ("checks_per_thread", ctypes.c_int32), ("stream", ctypes.c_void_p),
     ]
 
 
@@ -93,6 +103,19 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.ldpc_reconciliation_llr.argtypes = [I32, I32, I32, P, P, ctypes.c_float, P, P]
         lib.ldpc_reconciliation_message.restype = ctypes.c_int
         lib.ldpc_reconciliation_message.argtypes = [I32, I32, I32, P, P, P, P]
+        lib.ldpc_engine_create.restype = ctypes.c_int
+        lib.ldpc_engine_create.argtypes = [ctypes.POINTER(EngineConfig), ctypes.POINTER(P)]
+        lib.ldpc_engine_destroy.restype = None
+        lib.ldpc_engine_destroy.argtypes = [P]
+        lib.ldpc_engine_request_bytes.restype = ctypes.c_size_t
+        lib.ldpc_engine_request_bytes.argtypes = [P, I32, I32, I32]
+        lib.ldpc_engine_submit.restype = ctypes.c_int
+        lib.ldpc_engine_submit.argtypes = [P, P, I32, P, P, I32, P, P, P,
+                                           ctypes.POINTER(ctypes.c_int64)]
+        lib.ldpc_engine_step.restype = ctypes.c_int
+        lib.ldpc_engine_step.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        lib.ldpc_engine_poll.restype = ctypes.c_int
+        lib.ldpc_engine_poll.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I32, ctypes.POINTER(I32)]
         _lib = lib
         return lib
 
@@ -114,9 +137,10 @@ def _stream_handle(stream):
 
 
 def make_opts(early_stop=True, check_from_iter=0, msg_fp16=False, llr_out_ptr=None,
-              timing_events=None) -> DecodeOpts:
+              timing_events=None, checks_per_thread=0) -> DecodeOpts:
     o = DecodeOpts()
     load().ldpc_decode_opts_init(ctypes.byref(o))
+    o.checks_per_thread = int(checks_per_thread)
     o.early_stop = int(bool(early_stop))
     o.check_from_iter = int(check_from_iter)
     o.msg_fp16 = int(bool(msg_fp16))
@@ -174,7 +198,7 @@ class Code:
 
     def decode(self, llr, syndrome, max_iters: int, early_stop=True, check_from_iter=0,
                msg_fp16=False, want_llr=False, workspace=None, out=None, stream=None,
-               timing_events=None):
+               timing_events=None, checks_per_thread=0):
         """Decode frames llr [F][n] float32 / syndrome [F][m] uint8 (CUDA tensors).
 
         Returns (bits uint8 [F][n], iters int32 [F], converged uint8 [F], L or None),
@@ -201,7 +225,8 @@ class Code:
         if workspace is None:
             workspace = self.alloc_workspace(F, max_iters, msg_fp16, want_llr, dev)
         opts = make_opts(early_stop, check_from_iter, msg_fp16,
-                         L.data_ptr() if L is not None else None, timing_events)
+                         L.data_ptr() if L is not None else None, timing_events,
+                         checks_per_thread)
         st = load().ldpc_decode_batch(
             self._h, F, llr.data_ptr(), syndrome.data_ptr(), int(max_iters),
             bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ctypes.byref(opts),
@@ -256,3 +281,97 @@ def reconciliation_message(bits, y, d: int = 8, out=None, stream=None):
                                             _stream_handle(stream))
     _check(st, "ldpc_reconciliation_message")
     return out
+
+
+class Engine:
+    """Multi-request engine (ldpc_engine_*): continuous batching of decode requests.
+
+    ``submit`` queues a request and returns its ticket; ``step`` runs one engine
+    step (retire, admit, one iteration of every active request); ``poll``
+    returns the tickets whose outputs are complete.  The engine keeps every
+    submitted tensor alive until its ticket is reported.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, msg_fp16=False,
+                 early_stop=True, stream=None, checks_per_thread=0):
+        import torch
+        lib = load()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        cfg = EngineConfig(int(hbm_budget_bytes), int(max_slots), int(bool(msg_fp16)),
+                           int(bool(early_stop)), int(checks_per_thread), self.stream.cuda_stream)
+        h = ctypes.c_void_p()
+        _check(lib.ldpc_engine_create(ctypes.byref(cfg), ctypes.byref(h)), "ldpc_engine_create")
+        self._h = h
+        self.msg_fp16 = bool(msg_fp16)
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ldpc_engine_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def request_bytes(self, code: "Code", F: int, max_iters: int) -> int:
+        return int(load().ldpc_engine_request_bytes(code.handle, int(F), int(max_iters),
+                                                    int(self.msg_fp16)))
+
+    def submit(self, code: "Code", llr, syndrome, max_iters: int) -> int:
+        import torch
+        if llr.dtype != torch.float32 or syndrome.dtype != torch.uint8 or llr.dim() != 2:
+            raise TypeError("llr float32 [F][n] and syndrome uint8 [F][m] device tensors expected")
+        if llr.shape[1] != code.n or syndrome.shape != (llr.shape[0], code.m):
+            raise ValueError("frame shapes do not match the code")
+        llr, syndrome = llr.contiguous(), syndrome.contiguous()
+        F = llr.shape[0]
+        bits = torch.empty((F, code.n), dtype=torch.uint8, device=llr.device)
+        iters = torch.empty(F, dtype=torch.int32, device=llr.device)
+        conv = torch.empty(F, dtype=torch.uint8, device=llr.device)
+        t = ctypes.c_int64()
+        st = load().ldpc_engine_submit(self._h, code.handle, F, llr.data_ptr(), syndrome.data_ptr(),
+                                       int(max_iters), bits.data_ptr(), iters.data_ptr(),
+                                       conv.data_ptr(), ctypes.byref(t))
+        _check(st, "ldpc_engine_submit")
+        self._live[t.value] = (code, llr, syndrome, bits, iters, conv)
+        return t.value
+
+    def step(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().ldpc_engine_step(self._h, ctypes.byref(a), ctypes.byref(q)),
+               "ldpc_engine_step")
+        return a.value, q.value
+
+    def poll(self, capacity: int = 64):
+        buf = (ctypes.c_int64 * capacity)()
+        n = ctypes.c_int32()
+        _check(load().ldpc_engine_poll(self._h, buf, capacity, ctypes.byref(n)), "ldpc_engine_poll")
+        return [buf[i] for i in range(n.value)]
+
+    def result(self, ticket: int):
+        """(bits, iters, converged) tensors of a reported ticket; releases them."""
+        code, llr, syn, bits, iters, conv = self._live.pop(ticket)
+        return bits, iters, conv
+
+    def pending(self) -> int:
+        return len(self._live)
+
+    def drain(self, tickets, max_steps: int = 1_000_000):
+        """Step until every ticket in ``tickets`` is reported; returns {ticket: outputs}."""
+        import torch
+        want = set(tickets)
+        out = {}
+        for _ in range(max_steps):
+            for t in self.poll():
+                if t in want:
+                    out[t] = self.result(t)
+            if len(out) == len(want):
+                return out
+            active, queued = self.step()
+            if active == 0 and queued == 0:
+                torch.cuda.current_stream().synchronize()
+        raise RuntimeError("engine did not finish within max_steps")

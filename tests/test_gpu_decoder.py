@@ -389,3 +389,21 @@ def test_rows_with_several_degree_1_blocks(ldpc, oracle_mod):
         assert ok, worst
     bits, it, conv, L = _gpu_decode(g, Q, s, 30)
     check_decode_parity(o, Q, s, bits, it, conv, o.decode(Q, s, 30), 30)
+
+
+@pytest.mark.parametrize("Z", [64, 1000])
+def test_schedule_does_not_change_results(ldpc, oracle_mod, Z):
+    base = synth.template_base(144, Z, seed=1)
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    x, Q = synth.biawgn_frames(o.n, 3, -13.5, seed=Z)
+    s = o.syndrome(x)
+    _say("schedules", Z)
+    ref = _gpu_decode(g, Q, s, 40, want_llr=True)
+    for cpt in (1, 2, 4):
+        for fp16 in (False, True):
+            r = _gpu_decode(g, Q, s, 40, want_llr=True, checks_per_thread=cpt, msg_fp16=fp16)
+            if not fp16:
+                for u, v in zip(r, ref):
+                    assert np.array_equal(u, v), cpt
+    with pytest.raises(ldpc.LdpcError):
+        g.decode(_dev(Q), _dev(s), 5, checks_per_thread=3)

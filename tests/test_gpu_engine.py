@@ -1,0 +1,175 @@
+"""Multi-request engine: every request's outputs equal ldpc_decode_batch on the
+same inputs, bit for bit, whatever else is in flight."""
+import numpy as np
+import pytest
+
+from paper_1702_07740_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ldpc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_07740_amd import ldpc as mod
+    mod.load()
+    return mod
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _requests(ldpc, oracle_mod, seed):
+    """Requests of mixed rate, lifting size and frame count, in the waterfall."""
+    specs = [(0.02, 64, 3, -14.0), (0.05, 100, 2, -10.2), (0.1, 63, 4, -6.8),
+             (0.02, 128, 1, -13.8), (0.1, 200, 2, -7.0), (0.05, 64, 4, -10.0),
+             (0.02, 64, 2, -15.4), (0.1, 63, 1, -6.5)]
+    out = []
+    for i, (rate, Z, F, snr) in enumerate(specs):
+        base = synth.template_for_rate(rate, Z, seed=1)
+        g = ldpc.Code(base, Z)
+        o = oracle_mod.OracleCode(base, Z)
+        x, Q = synth.biawgn_frames(o.n, F, snr, seed=seed * 100 + i)
+        s = o.syndrome(x)
+        out.append((g, _dev(Q), _dev(s), 60 if i % 3 else 40))
+    return out
+
+
+def _alone(g, Q, s, T, fp16):
+    bits, it, conv, _ = g.decode(Q, s, T, msg_fp16=fp16)
+    torch.cuda.synchronize()
+    return bits.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy()
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+def test_engine_results_equal_decode_batch(ldpc, oracle_mod, fp16):
+    reqs = _requests(ldpc, oracle_mod, 1)
+    eng = ldpc.Engine(1 << 30, max_slots=8, msg_fp16=fp16)
+    _say("engine vs alone", "fp16" if fp16 else "fp32")
+    tickets = []
+    # staggered arrivals: some now, the rest while the first ones decode
+    for i, (g, Q, s, T) in enumerate(reqs):
+        tickets.append(eng.submit(g, Q, s, T))
+        if i % 2 == 1:
+            for _ in range(7):
+                eng.step()
+    res = eng.drain(tickets)
+    for (g, Q, s, T), t in zip(reqs, tickets):
+        bits, it, conv = (r.cpu().numpy() for r in res[t])
+        b0, i0, c0 = _alone(g, Q, s, T, fp16)
+        assert np.array_equal(bits, b0) and np.array_equal(it, i0) and np.array_equal(conv, c0)
+    assert any(res[t][2].cpu().numpy().any() for t in tickets)     # some frames converged
+    eng.close()
+
+
+def test_engine_budget_bounds_admission(ldpc, oracle_mod):
+    """Equal-size requests and a budget of 2.5 requests: never more than 2 in flight."""
+    Z, F, T = 128, 2, 50
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    reqs = []
+    for i in range(7):
+        x, Q = synth.biawgn_frames(o.n, F, -13.8, seed=700 + i)
+        reqs.append((_dev(Q), _dev(o.syndrome(x))))
+    probe = ldpc.Engine(1 << 20, 1)
+    need = probe.request_bytes(g, F, T)
+    probe.close()
+    eng = ldpc.Engine(2 * need + need // 2, max_slots=8)
+    _say("engine budget", 2 * need + need // 2)
+    tickets = [eng.submit(g, Q, s, T) for Q, s in reqs]
+    most = 0
+    done = {}
+    for _ in range(100000):
+        for t in eng.poll():
+            done[t] = eng.result(t)
+        if len(done) == len(tickets):
+            break
+        active, queued = eng.step()
+        most = max(most, active)
+        if active == 0 and queued == 0:
+            torch.cuda.synchronize()
+    assert len(done) == len(tickets)
+    assert most == 2
+    for (Q, s), t in zip(reqs, tickets):
+        b0, i0, c0 = _alone(g, Q, s, T, False)
+        assert np.array_equal(done[t][0].cpu().numpy(), b0)
+        assert np.array_equal(done[t][1].cpu().numpy(), i0)
+    # a request larger than the whole budget is refused at submit
+    with pytest.raises(ldpc.LdpcError):
+        eng.submit(g, torch.cat([reqs[0][0]] * 6), torch.cat([reqs[0][1]] * 6), T)
+    eng.close()
+
+
+def test_engine_edge_cases(ldpc, oracle_mod):
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    x, Q = synth.biawgn_frames(o.n, 3, -13.0, seed=5)
+    s = o.syndrome(x)
+    Q[1] = synth.noiseless_llr(x[1], 3.0)
+    dQ, ds = _dev(Q), _dev(s)
+    eng = ldpc.Engine(1 << 28, max_slots=2)
+    _say("engine edge cases")
+    t0 = eng.submit(g, dQ, ds, 0)          # max_iters = 0
+    t1 = eng.submit(g, dQ[1:2], ds[1:2], 50)  # noiseless frame: 0 iterations
+    t2 = eng.submit(g, dQ, ds, 1)
+    res = eng.drain([t0, t1, t2])
+    for t, (QQ, ss, T) in ((t0, (dQ, ds, 0)), (t1, (dQ[1:2], ds[1:2], 50)), (t2, (dQ, ds, 1))):
+        b0, i0, c0 = _alone(g, QQ, ss, T, False)
+        assert np.array_equal(res[t][0].cpu().numpy(), b0)
+        assert np.array_equal(res[t][1].cpu().numpy(), i0)
+        assert np.array_equal(res[t][2].cpu().numpy(), c0)
+    assert int(res[t1][1].cpu()[0]) == 0
+    # a code with a row the engine does not take
+    gen = np.full((2, 12), -1, dtype=np.int32)
+    gen[0, :9] = 0
+    gen[1, [0, 1]] = 1
+    with pytest.raises(ldpc.LdpcError):
+        eng.submit(ldpc.Code(gen, 4), torch.zeros((1, 48), device="cuda"),
+                   torch.zeros((1, 8), dtype=torch.uint8, device="cuda"), 5)
+    eng.close()
+
+
+def test_serving_results_same_alone_and_in_the_mix(ldpc):
+    """A Poisson trace of mixed-code requests served with continuous batching:
+    every request's outputs equal the same request decoded alone."""
+    import copy
+    from paper_1702_07740_amd import serve
+    pools = serve.make_pools(ldpc, torch, lifts=(64, 128), frames_per_pool=8)
+    trace = serve.poisson_trace(len(pools), 400.0, 0.15, seed=3)
+    assert len(trace) >= 20
+    _say("serving trace", len(trace))
+    st, mixed = serve.run_engine(ldpc, torch, pools, copy.deepcopy(trace), 64 << 20,
+                                 max_slots=6, keep_outputs=True)
+    assert st["requests"] == len(trace)
+    assert st["peak_in_flight"] >= 2            # requests overlapped on the device
+    tr2 = copy.deepcopy(trace)
+    _, alone = serve.run_one_at_a_time(ldpc, torch, pools, tr2, keep_outputs=True)
+    assert sorted(mixed) == sorted(alone) == list(range(len(trace)))
+    for i in range(len(trace)):
+        for u, v in zip(mixed[i], alone[i]):
+            assert np.array_equal(u, v), f"request {i} differs"
+
+
+@pytest.mark.parametrize("cpt", [1, 2])
+def test_engine_schedule_does_not_change_results(ldpc, oracle_mod, cpt):
+    reqs = _requests(ldpc, oracle_mod, 4)[:4]
+    eng = ldpc.Engine(1 << 30, max_slots=8, checks_per_thread=cpt)
+    _say("engine schedule", cpt)
+    tickets = [eng.submit(g, Q, s, T) for g, Q, s, T in reqs]
+    res = eng.drain(tickets)
+    for (g, Q, s, T), t in zip(reqs, tickets):
+        b0, i0, c0 = _alone(g, Q, s, T, False)
+        assert np.array_equal(res[t][0].cpu().numpy(), b0)
+        assert np.array_equal(res[t][1].cpu().numpy(), i0)
+    eng.close()
