@@ -70,7 +70,9 @@ typedef struct {
  * block (r, c) joins check r*Z + a to variable c*Z + ((a + shift) mod Z).
  *   mb, nb  base shape, >= 1
  *   base    host, mb*nb int32 row-major; -1 = zero block, else shift in [0, Z)
- *   Z       lifting size, 1 <= Z, with nb*Z and mb*Z < 2^31
+ *   Z       lifting size, 1 <= Z; n = nb*Z, m = mb*Z, the stored edges and twice
+ *           the core variables (+ padding) of one frame must each stay below
+ *           2^30 - 1024 (32-bit byte offsets), else LDPC_EINVAL
  *   out     host; receives the handle (set to NULL on failure)
  * Builds the block tables (row lists, column lists, degree classes) and copies
  * them to the current HIP device, to which the handle is bound.

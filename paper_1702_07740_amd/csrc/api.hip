@@ -155,6 +155,18 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     const int NS = (int)st_row.size(), NC = (int)core_col.size(), ND1 = (int)d1_col.size();
     if (mb > 65535 || NC > 65535)  // base rows and core columns index grid.y
         return fail_with(LDPC_EUNSUPPORTED, "more than 65535 base rows or core columns");
+    {
+        // every per-frame array is addressed with 32-bit byte offsets
+        const int64_t lim = (1ll << 30) - ldpc::kLanePad;
+        const int64_t zt = ((2ll * Z + ldpc::kLanePad) + 63) / 64 * 64;
+        const int64_t zp = ((int64_t)Z + 63) / 64 * 64;
+        if ((int64_t)nb * Z >= lim || (int64_t)mb * Z >= lim || (int64_t)NS * zp >= lim ||
+            (int64_t)ND1 * zp >= lim || (int64_t)NC * zt >= lim)
+            return fail_with(LDPC_EINVAL,
+                             "code too large: n, m, stored edges and 2 x core variables per "
+                             "frame must stay below 2^30 - %d",
+                             ldpc::kLanePad);
+    }
     // per core column: its state blocks in increasing row order
     std::vector<int32_t> core_first(NC), core_deg(NC, 0), core_state(NS), core_shift(NS);
     for (int i = 0; i < NS; ++i) core_deg[st_core[i]]++;
@@ -192,13 +204,43 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     auto common = [&](int r) {
         return row_deg[r] <= ldpc::kSmallRowDegree && row_ns[r] >= row_deg[r] - 1;
     };
+    // common rows grouped by (degree, stored blocks) class, then the others
+    auto cls_of = [&](int r) { return 2 * (row_deg[r] - 1) + (row_ns[r] - (row_deg[r] - 1)); };
     std::vector<int32_t> row_list;
-    for (int r = 0; r < mb; ++r)
-        if (common(r)) row_list.push_back(r);
+    int32_t cls_end[ldpc::kFixedClasses];
+    for (int cl = 0; cl < ldpc::kFixedClasses; ++cl) {
+        for (int r = 0; r < mb; ++r)
+            if (common(r) && cls_of(r) == cl) row_list.push_back(r);
+        cls_end[cl] = (int32_t)row_list.size();
+    }
     const int n_small = (int)row_list.size();
     for (int r = 0; r < mb; ++r)
         if (!common(r)) row_list.push_back(r);
     const size_t o_rl = put(row_list);
+    // descriptors of the common rows (offsets within one frame's arrays)
+    const int32_t Zt = ((2 * Z + ldpc::kLanePad) + 63) / 64 * 64;
+    const int32_t W = (Z + 63) / 64;
+    const int32_t Zp = (Z + 63) / 64 * 64;
+    std::vector<int32_t> row_desc((size_t)std::max(n_small, 1) * ldpc::kRowDescWords, 0);
+    for (int y = 0; y < n_small; ++y) {
+        const int r = row_list[y];
+        int32_t *dd = &row_desc[(size_t)y * ldpc::kRowDescWords];
+        for (int k = 0; k < row_deg[r]; ++k) {
+            const int b = row_first[r] + k;
+            if (k < row_ns[r]) {
+                dd[k] = blk_core[b] * Zt + blk_shift[b];
+                dd[6 + k] = blk_ref[b] * Zp;
+            } else {
+                dd[12] = blk_ref[b] * Zp;
+                dd[13] = blk_ref[b] * W;
+                dd[14] = blk_col[b] * Z;
+                dd[15] = blk_shift[b];
+            }
+        }
+        dd[16] = r * W;
+        dd[17] = r;
+    }
+    const size_t o_rd = put(row_desc);
 
     ldpc_code *code = new (std::nothrow) ldpc_code();
     if (!code) return fail_with(LDPC_ENOMEM, "host allocation failed");
@@ -230,6 +272,8 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.NC = NC;
     d.ND1 = ND1;
     d.W = (Z + 63) / 64;
+    d.Zt = Zt;
+    d.Zp = Zp;
     d.row_first = T + o_row_first;
     d.row_deg = T + o_row_deg;
     d.row_ns = T + o_row_ns;
@@ -238,6 +282,8 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     for (int k = 0; k < NC; ++k) d.max_core_deg = std::max(d.max_core_deg, core_deg[k]);
     d.n_small = n_small;
     d.n_large = mb - n_small;
+    for (int cl = 0; cl < ldpc::kFixedClasses; ++cl) d.cls_end[cl] = cls_end[cl];
+    d.row_desc = T + o_rd;
     d.blk_shift = T + o_bs;
     d.blk_kind = T + o_bk;
     d.blk_ref = T + o_br;

@@ -43,52 +43,70 @@ using namespace dev;
 // One launch covers the rows of one degree class; grid.y walks that class's
 // rows in the row list.
 template <typename Msg, bool kLarge, int MODE, int CPT>
-__global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A) {
-    const int f = blockIdx.z;
-    const int r = c.row_list[(kLarge ? c.n_small : 0) + (int)blockIdx.y];
-    if (A.skip_after >= 0 && A.fail[(size_t)A.skip_after * A.F + f] == 0) return;
-    check_work<Msg, kLarge, MODE, CPT>(c, A, f, r, blockIdx.x);
+__global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, unsigned tiles,
+                                                     unsigned rows) {
+    const unsigned n = tiles * rows * (unsigned)A.F;
+    unsigned i = xcd_item(blockIdx.x, n);
+    if (i >= n) return;
+    const unsigned tile = i % tiles;
+    i /= tiles;
+    const int y = (kLarge ? c.n_small : 0) + (int)(i % rows);
+    check_work<Msg, kLarge, MODE, CPT>(c, A, (int)(i / rows), y, tile);
 }
 
 // Common rows run with the requested checks per thread (1, 2 or 4); the rare
-// generic rows always with the default.
+// generic rows, and launches that also write posteriors, with the default.
 template <typename Msg, int MODE>
 void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, int cpt, hipStream_t st) {
     if (c.n_small > 0) {
-        const dim3 g(check_tiles(c.Z, cpt), c.n_small, F);
-        if (cpt == 1)
-            check_pass<Msg, false, MODE, 1><<<g, dim3(kBlock), 0, st>>>(c, a);
-        else if (cpt == 2)
-            check_pass<Msg, false, MODE, 2><<<g, dim3(kBlock), 0, st>>>(c, a);
-        else
-            check_pass<Msg, false, MODE, 4><<<g, dim3(kBlock), 0, st>>>(c, a);
+        if constexpr (with_post(MODE)) cpt = kDefaultChecksPerThread;
+        const unsigned tl = check_tiles(c.Z, cpt), rows = (unsigned)c.n_small;
+        const dim3 g(xcd_grid(tl * rows * (unsigned)F));
+        if constexpr (with_post(MODE)) {
+            check_pass<Msg, false, MODE, kDefaultChecksPerThread><<<g, dim3(kBlock), 0, st>>>(c, a, tl, rows);
+        } else {
+            if (cpt == 1)
+                check_pass<Msg, false, MODE, 1><<<g, dim3(kBlock), 0, st>>>(c, a, tl, rows);
+            else if (cpt == 2)
+                check_pass<Msg, false, MODE, 2><<<g, dim3(kBlock), 0, st>>>(c, a, tl, rows);
+            else
+                check_pass<Msg, false, MODE, 4><<<g, dim3(kBlock), 0, st>>>(c, a, tl, rows);
+        }
     }
-    if (c.n_large > 0)
+    if (c.n_large > 0) {
+        const unsigned tl = check_tiles(c.Z, kDefaultChecksPerThread), rows = (unsigned)c.n_large;
         check_pass<Msg, true, MODE, kDefaultChecksPerThread>
-            <<<dim3(check_tiles(c.Z, kDefaultChecksPerThread), c.n_large, F), dim3(kBlock), 0, st>>>(c, a);
+            <<<dim3(xcd_grid(tl * rows * (unsigned)F)), dim3(kBlock), 0, st>>>(c, a, tl, rows);
+    }
 }
 
 template <int U, typename Msg>
-__global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A) {
-    const int f = blockIdx.z;
+__global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A, unsigned tiles) {
+    const unsigned n = tiles * (unsigned)c.NC * (unsigned)A.F;
+    unsigned i = xcd_item(blockIdx.x, n);
+    if (i >= n) return;
+    const unsigned tile = i % tiles;
+    i /= tiles;
+    const int f = (int)(i / (unsigned)c.NC);
     if (A.fail[(size_t)(A.t - 1) * A.F + f] == 0) return;
-    variable_work<U, Msg>(c, A, f, blockIdx.y, blockIdx.x);
+    variable_work<U, Msg>(c, A, f, (int)(i % (unsigned)c.NC), tile);
 }
 
 // Batch width of the variable pass: batches of about 20 loads (measured: wider
 // batches flood the memory pipeline, padded slots cost real loads), sized so
 // that they divide the column degree with little padding, e.g. 3 x 17 for 51.
 template <typename Msg>
-void launch_variable_pass(const CodeDev &c, const VnArgs &v, const dim3 &grid, hipStream_t st) {
+void launch_variable_pass(const CodeDev &c, const VnArgs &v, int F, hipStream_t st) {
     const int u = variable_batch(c.max_core_deg);
-    const dim3 b(kBlock);
+    const unsigned tl = (unsigned)((c.Z + kBlock - 1) / kBlock);
+    const dim3 grid(xcd_grid(tl * (unsigned)c.NC * (unsigned)F)), b(kBlock);
     switch (u) {
-        case 8: variable_pass<8, Msg><<<grid, b, 0, st>>>(c, v); break;
-        case 11: variable_pass<11, Msg><<<grid, b, 0, st>>>(c, v); break;
-        case 16: variable_pass<16, Msg><<<grid, b, 0, st>>>(c, v); break;
-        case 17: variable_pass<17, Msg><<<grid, b, 0, st>>>(c, v); break;
-        case 21: variable_pass<21, Msg><<<grid, b, 0, st>>>(c, v); break;
-        default: variable_pass<26, Msg><<<grid, b, 0, st>>>(c, v); break;
+        case 8: variable_pass<8, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
+        case 11: variable_pass<11, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
+        case 16: variable_pass<16, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
+        case 17: variable_pass<17, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
+        case 21: variable_pass<21, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
+        default: variable_pass<26, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
     }
 }
 
@@ -194,7 +212,6 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     v.msg_frame = L.msg_frame;
     v.tot_frame = L.tot_frame;
     v.F = F;
-    const dim3 vn_grid(tiles(c.Z), c.NC, F);
 
     for (int t = 1; t <= T; ++t) {
         a.t = t;
@@ -205,14 +222,21 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
         a.d1post = d1p[t & 1];
         a.skip_after = t >= 2 ? t - 2 : -1;
         if (l.events) (void)hipEventRecord(l.events[2 * (t - 1)], st);
-        if (t == 1)
-            launch_check_pass<Msg, kFirst>(c, a, F, l.cpt, st);
-        else
-            launch_check_pass<Msg, kSteady>(c, a, F, l.cpt, st);
+        if (t == 1) {
+            if (a.d1post)
+                launch_check_pass<Msg, kFirst | kPost>(c, a, F, l.cpt, st);
+            else
+                launch_check_pass<Msg, kFirst>(c, a, F, l.cpt, st);
+        } else {
+            if (a.d1post)
+                launch_check_pass<Msg, kSteady | kPost>(c, a, F, l.cpt, st);
+            else
+                launch_check_pass<Msg, kSteady>(c, a, F, l.cpt, st);
+        }
         if (l.events) (void)hipEventRecord(l.events[2 * (t - 1) + 1], st);
         if (c.NC > 0) {
             v.t = t;
-            launch_variable_pass<Msg>(c, v, vn_grid, st);
+            launch_variable_pass<Msg>(c, v, F, st);
         }
     }
     if (l.events) (void)hipEventRecord(l.events[2 * T], st);
@@ -252,19 +276,18 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
 
 WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr) {
     WorkLayout L{};
-    const size_t Z = (size_t)c.Z;
-    L.msg_frame = (size_t)c.NS * Z;
-    L.tot_frame = (size_t)c.NC * Z;
+    L.msg_frame = (size_t)c.NS * c.Zp;
+    L.tot_frame = (size_t)c.NC * c.Zt;
     L.d1bits_frame = (size_t)c.ND1 * c.W;
     L.synbits_frame = (size_t)c.mb * c.W;
-    L.psi_frame = (size_t)c.ND1 * Z;
+    L.psi_frame = (size_t)c.ND1 * c.Zp;
     size_t off = 0;
     L.msg = off;
-    off = align256(off + (size_t)F * L.msg_frame * (fp16 ? 2 : 4));
+    off = align256(off + ((size_t)F * L.msg_frame + kLanePad) * (fp16 ? 2 : 4));
     L.tot = off;
     off = align256(off + (size_t)F * L.tot_frame * 4);
     L.psi = off;
-    off = align256(off + (size_t)F * L.psi_frame * 4);
+    off = align256(off + ((size_t)F * L.psi_frame + kLanePad) * 4);
     L.d1bits = off;
     off = align256(off + 2 * (size_t)F * L.d1bits_frame * 8);
     L.synbits = off;

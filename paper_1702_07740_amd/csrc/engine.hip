@@ -61,7 +61,8 @@ __device__ __forceinline__ bool checked_iter(const SlotDesc &S, int t) {
 template <typename Msg, int CPT>
 __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slots, SlotIndex ix,
                                                             int step) {
-    const int item = blockIdx.x;
+    const int item = (int)xcd_item(blockIdx.x, (unsigned)ix.begin[ix.n]);
+    if (item >= ix.begin[ix.n]) return;
     const int s = find_slot(ix, item);
     const SlotDesc &S = slots[s];
     const int t = step - S.start_step + 1;
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
     int local = item - ix.begin[s];
     const unsigned tile = (unsigned)(local % S.cn_tiles);
     local /= S.cn_tiles;
-    const int r = S.c.row_list[local % S.c.mb];
+    const int y = local % S.c.mb;  // row_list position (every row of an engine code is common)
     const int f = local / S.c.mb;
     const bool vote_only = t == S.T + 1;
     CnArgs A{};
@@ -101,19 +102,19 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
         A.d1_cur = S.d1b[t & 1];
         A.skip_after = t >= 2 ? t - 2 : -1;
     }
-    if (A.skip_after >= 0 && A.fail[(size_t)A.skip_after * A.F + f] == 0) return;
     if (vote_only)
-        check_work<Msg, false, kVoteOnly, CPT>(S.c, A, f, r, tile);
+        check_work<Msg, false, kVoteOnly, CPT>(S.c, A, f, y, tile);
     else if (t == 1)
-        check_work<Msg, false, kFirst, CPT>(S.c, A, f, r, tile);
+        check_work<Msg, false, kFirst, CPT>(S.c, A, f, y, tile);
     else
-        check_work<Msg, false, kSteady, CPT>(S.c, A, f, r, tile);
+        check_work<Msg, false, kSteady, CPT>(S.c, A, f, y, tile);
 }
 
 template <typename Msg, int U>
 __global__ __launch_bounds__(kBlock) void engine_variable_pass(const SlotDesc *slots, SlotIndex ix,
                                                                int step) {
-    const int item = blockIdx.x;
+    const int item = (int)xcd_item(blockIdx.x, (unsigned)ix.begin[ix.n]);
+    if (item >= ix.begin[ix.n]) return;
     const int s = find_slot(ix, item);
     const SlotDesc &S = slots[s];
     const int t = step - S.start_step + 1;
@@ -474,7 +475,7 @@ hipError_t Engine::step(int *active_out, int *queued_out) {
         int max_deg = 0;
         for (int i = 0; i < n; ++i) max_deg = std::max(max_deg, slot[order[i]].desc.c.max_core_deg);
         // 5. one iteration of every active slot, then the status copy
-        const dim3 gc(cn_total), gv(vn_total), b(kBlock);
+        const dim3 gc(xcd_grid((unsigned)cn_total)), gv(xcd_grid((unsigned)vn_total)), b(kBlock);
         if (fp16) {
             if (cpt == 1) engine_check_pass<_Float16, 1><<<gc, b, 0, stream>>>(d_slots, cn, step_no);
             else if (cpt == 2) engine_check_pass<_Float16, 2><<<gc, b, 0, stream>>>(d_slots, cn, step_no);

@@ -26,18 +26,37 @@ enum : int32_t { COL_CORE = 0, COL_DEG1 = 1, COL_DEG0 = 2 };
 // so their register needs do not lower the occupancy of the common rows.
 constexpr int kSmallRowDegree = 6;
 
-// Default checks per thread of the common-row check kernel.
+// Common rows come in 2 * kSmallRowDegree classes (degree D, stored blocks
+// D - 1 or D); class index 2 (D - 1) + (stored - (D - 1)).
+constexpr int kFixedClasses = 2 * kSmallRowDegree;
+// Words of a common row's descriptor (see CodeDev::row_desc).
+constexpr int kRowDescWords = 20;
+
+// Default and largest checks per thread of the common-row check kernel.
 constexpr int kDefaultChecksPerThread = 4;
+constexpr int kMaxChecksPerThread = 4;
+
+// Elements read past the end of a per-block array by the padding lanes of the
+// last check tile of a row (256 threads x 4 checks); the message and degree-1
+// regions carry this much slack.
+constexpr int kLanePad = 256 * kMaxChecksPerThread;
 
 // Device view of a code: sizes plus pointers into small device tables.  Passed
 // by value as a kernel argument; every table index below is uniform across a
 // workgroup, so the loads are scalar.
 struct CodeDev {
     int32_t Z, mb, nb, n, m;
-    int32_t NS;   // state blocks (messages per frame = NS * Z)
+    int32_t NS;   // state blocks (messages per frame = NS * Zp)
     int32_t NC;   // core columns (degree >= 2)
     int32_t ND1;  // degree-1 columns (= degree-1 blocks)
     int32_t W;    // 64-bit words per Z bits
+    // Row stride of the core totals: row k holds L[j] at j and again at j + Z,
+    // so a check gathers position (a + s) mod Z as index a + s without a wrap;
+    // kLanePad more slots keep padding lanes in bounds.
+    int32_t Zt;
+    // Stride of the per-block arrays (messages, Psi, degree-1 posteriors): Z
+    // rounded up to 64, so every block starts on a 256-byte boundary.
+    int32_t Zp;
     // per base row r: blocks row_first[r] .. row_first[r] + row_deg[r] - 1;
     // the first row_ns[r] are blocks of columns of degree >= 2 (stored
     // messages), the rest degree-1 blocks, each group in column order
@@ -46,6 +65,16 @@ struct CodeDev {
     // <= kSmallRowDegree, at most one degree-1 block) first, then the n_large others
     const int32_t *row_list;
     int32_t n_small, n_large;
+    // the common rows are grouped by class in row_list: class i holds positions
+    // cls_end[i-1] .. cls_end[i] - 1 (cls_end[-1] = 0)
+    int32_t cls_end[kFixedClasses];
+    // per common row (row_list position y), kRowDescWords words at y * kRowDescWords:
+    //   [0, 6)  stored block k: offset of its column's totals + shift (core * Zt + s)
+    //   [6, 12) stored block k: offset of its messages (state index * Zp)
+    //   12..15  degree-1 block: Psi offset (index * Zp), decision-word offset
+    //           (index * W), channel-LLR offset (column * Z), shift
+    //   16, 17  syndrome-word offset (r * W), base row r
+    const int32_t *row_desc;
     // per block: shift, kind, ref (state index or degree-1 index), column,
     // core index of the column (state blocks only, else -1)
     const int32_t *blk_shift, *blk_kind, *blk_ref, *blk_col, *blk_core;

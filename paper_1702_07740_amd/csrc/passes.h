@@ -13,39 +13,77 @@ namespace ldpc {
 namespace dev {
 
 constexpr int kBlock = 256;  // threads per workgroup: 4 wave64s
+
+// Work items of a launch in XCD-aware order.  The hardware hands consecutive
+// workgroups to the chip's 8 XCDs in turn, and each XCD has its own L2.
+// Workgroup g takes item (g mod 8) * per + g / 8, so XCD x runs the
+// contiguous items [x per, (x + 1) per): items that share data (one frame's
+// core totals, the lines at the edges of neighbouring tiles) meet in one L2.
+constexpr unsigned kXcds = 8;
+inline unsigned xcd_grid(unsigned n) { return (n + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ unsigned xcd_item(unsigned g, unsigned n) {
+    const unsigned per = (n + kXcds - 1) / kXcds;
+    return (g % kXcds) * per + g / kXcds;
+}
 constexpr float kPhiLo = 1e-7f;
 constexpr float kPhiHi = 30.0f;
 
 // Phi(x) = -ln tanh(x/2) on the clamped argument [1e-7, 30], branch-free:
-//   x <  2: Phi(x) = ln 2 - ln x + g(x^2/4), where g(u) = -ln(tanh(y)/y),
-//           y = sqrt(u), is smooth and even; g(w/4) = w H(w) with H a degree-6
-//           least-squares fit on [0, 4] (absolute error 3e-9);
-//   x >= 2: Phi(x) = 2 atanh(t), t = e^{-x} <= 0.136, by its odd series to t^9
-//           (truncation below 3e-10 relative; no cancellation for large x).
+//   x <  2.25: Phi(x) = ln 2 - ln x + g(x^2/4), where g(u) = -ln(tanh(y)/y),
+//              y = sqrt(u), is smooth and even; g(w/4) = w H(w) with H a
+//              degree-5 near-minimax fit on w in [0, 5.07) (relative error of
+//              the fit below 8e-8 of Phi);
+//   x >= 2.25: Phi(x) = 2 atanh(t), t = e^{-x} <= 0.106, by its odd series to
+//              t^5 (truncation below 2e-7 relative; no cancellation for large x).
 // Both branches use one hardware transcendental (log2 or exp2).  Relative
-// error below 1e-6 for x < 20 and below 2e-6 up to 30 (there Phi < 2e-9).
-__device__ __forceinline__ float phi_f32(float x) {
+// error in FP32 below 1e-6 for x < 20 and below 2e-6 up to 30 (there
+// Phi < 2e-9).
+// The polynomial coefficients that cannot ride in an instruction's literal
+// field (an FMA takes one literal), held in registers for a whole launch.
+// Each is passed through an empty asm statement once, so the compiler keeps
+// it in a register instead of re-materialising it before every use.
+struct PhiConsts {
+    float h5, h4, h3, h2, h1, h0, ln2, q1, hi;
+};
+
+__device__ __forceinline__ float opaque(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+__device__ __forceinline__ PhiConsts phi_consts() {
+    PhiConsts K;
+    K.h5 = opaque(-4.600071435e-08f);
+    K.h4 = opaque(1.415273005e-06f);
+    K.h3 = opaque(-2.400134144e-05f);
+    K.h2 = opaque(3.378146503e-04f);
+    K.h1 = opaque(-4.857770633e-03f);
+    K.h0 = opaque(8.333229274e-02f);
+    K.ln2 = opaque(0.6931471805599453f);
+    K.q1 = opaque(2.0f / 3.0f);
+    K.hi = opaque(kPhiHi);
+    return K;
+}
+
+__device__ __forceinline__ float phi_f32(float x, const PhiConsts &K) {
     constexpr float kLog2e = 1.4426950408889634f;
     constexpr float kLn2 = 0.6931471805599453f;
-    x = __builtin_amdgcn_fmed3f(x, kPhiLo, kPhiHi);
+    x = __builtin_amdgcn_fmed3f(x, kPhiLo, K.hi);
     const float w = x * x;
-    float h = 5.28133137e-09f;
-    h = fmaf(w, h, -1.35732463e-07f);
-    h = fmaf(w, h, 2.02647516e-06f);
-    h = fmaf(w, h, -2.61091045e-05f);
-    h = fmaf(w, h, 3.41622334e-04f);
-    h = fmaf(w, h, -4.86108987e-03f);
-    h = fmaf(w, h, 8.33333358e-02f);
-    const float small = fmaf(-kLn2, __builtin_amdgcn_logf(x), kLn2) + w * h;
+    float h = fmaf(w, K.h5, K.h4);
+    h = fmaf(h, w, K.h3);
+    h = fmaf(h, w, K.h2);
+    h = fmaf(h, w, K.h1);
+    h = fmaf(h, w, K.h0);
+    const float small = fmaf(-kLn2, __builtin_amdgcn_logf(x), fmaf(h, w, K.ln2));
     const float t = __builtin_amdgcn_exp2f(-x * kLog2e);
     const float t2 = t * t;
-    float p = fmaf(t2, 2.0f / 9.0f, 2.0f / 7.0f);
-    p = fmaf(t2, p, 2.0f / 5.0f);
-    p = fmaf(t2, p, 2.0f / 3.0f);
-    p = fmaf(t2, p, 2.0f);
+    const float p = fmaf(t2, fmaf(t2, 2.0f / 5.0f, K.q1), 2.0f);
     const float large = t * p;
-    return x < 2.0f ? small : large;
+    return x < 2.25f ? small : large;
 }
+
+__device__ __forceinline__ float phi_f32(float x) { return phi_f32(x, phi_consts()); }
 
 template <typename Msg> __device__ __forceinline__ float msg_load(const Msg *p);
 template <> __device__ __forceinline__ float msg_load<float>(const float *p) { return *p; }
@@ -102,8 +140,8 @@ struct RowCtx {
     float *d1post;            // frame's degree-1 posteriors (or null)
     const uint64_t *syn;      // this row's packed syndrome words
     unsigned shift[D];        // circulant shift of each block
-    unsigned off[D];          // state: msg offset ref*Z; degree-1: psi offset ref*Z
-    unsigned src[D];          // state: totals offset core*Z; degree-1: llr offset col*Z
+    unsigned off[D];          // state: msg offset ref*Zp; degree-1: psi offset ref*Zp
+    unsigned src[D];          // state: totals offset core*Zt; degree-1: llr offset col*Z
     unsigned wrd[D];          // degree-1: decision-word offset ref*W
     int ns;                   // blocks 0..ns-1 keep stored messages, the rest are degree-1
     unsigned Z, W;
@@ -132,8 +170,8 @@ __device__ __forceinline__ RowCtx<D, Msg> load_row(const CodeDev &c, const CnArg
         const bool st = k < R.ns;
         const unsigned ref = (unsigned)c.blk_ref[b];
         R.shift[k] = (unsigned)c.blk_shift[b];
-        R.off[k] = ref * Z;
-        R.src[k] = (unsigned)(st ? c.blk_core[b] : c.blk_col[b]) * Z;
+        R.off[k] = ref * (unsigned)c.Zp;
+        R.src[k] = st ? (unsigned)c.blk_core[b] * (unsigned)c.Zt : (unsigned)c.blk_col[b] * Z;
         R.wrd[k] = ref * R.W;
     }
     return R;
@@ -164,7 +202,10 @@ enum : int {
     kSteady = 0,    // iteration t >= 2: read the old messages, vote t-1 from stored bits
     kFirst = 1,     // iteration 1: old messages are zero, vote t = 0 from the channel signs
     kVoteOnly = 2,  // no update: only the parity check of the last iteration
+    kPost = 4,      // flag on kSteady / kFirst: also write degree-1 posteriors Q + m
 };
+constexpr int base_mode(int mode) { return mode & 3; }
+constexpr bool with_post(int mode) { return (mode & kPost) != 0; }
 
 // K checks (r, a_first + q*256), q < K, of one frame, row degree D with DS
 // stored blocks.  Padding lanes (a >= Z) load from a clamped in-range index,
@@ -194,15 +235,15 @@ __device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs
             if (stored<DS>(R, k)) {
                 const float lt = at(R.tot, R.src[k] + j);
                 dec = lt < 0.0f;
-                const float mo = (MODE == kSteady) ? msg_load<Msg>(&at(R.msg, R.off[k] + al)) : 0.0f;
+                const float mo = (base_mode(MODE) == kSteady) ? msg_load<Msg>(&at(R.msg, R.off[k] + al)) : 0.0f;
                 xv = lt - mo;
             } else {
                 xv = at(R.psi, R.off[k] + al);
-                if (MODE == kFirst) {
+                if (base_mode(MODE) == kFirst) {
                     dec = xv < 0.0f;
                 } else {
                     const int db = (int)((at(R.d1_prev, R.wrd[k] + w) >> bit) & 1ull);
-                    dec = (MODE == kVoteOnly && A.d1_from_llr) ? (xv < 0.0f) : db;
+                    dec = (base_mode(MODE) == kVoteOnly && A.d1_from_llr) ? (xv < 0.0f) : db;
                 }
             }
             x[q][k] = xv;
@@ -213,7 +254,7 @@ __device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs
     int bad = 0;
 #pragma unroll
     for (int q = 0; q < K; ++q) bad |= vpar[q];
-    if (MODE == kVoteOnly) return bad;
+    if (base_mode(MODE) == kVoteOnly) return bad;
 
 #pragma unroll
     for (int q = 0; q < K; ++q) {
@@ -254,7 +295,7 @@ __device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs
                 const int dec = (negq == sgn) ? negq : (ph[k] < S ? negq : sgn);
                 const unsigned long long bits = wave_ballot(valid && dec);
                 if ((threadIdx.x & 63) == 0 && valid) at(R.d1_cur, R.wrd[k] + w) = bits;
-                if (R.d1post && valid) {
+                if (with_post(MODE) && R.d1post && valid) {
                     unsigned j = a + R.shift[k];
                     j -= (j >= Z) ? Z : 0u;
                     const float mag = phi_f32(ex[k]);
@@ -266,51 +307,286 @@ __device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs
     return bad;
 }
 
+// Bit l of a wave-uniform 64-bit word as lane l's predicate: the word is used
+// directly as a lane mask, with no per-lane shift.
+__device__ __forceinline__ bool lane_bit(uint64_t word) {
+    return __builtin_amdgcn_inverse_ballot_w64(word);
+}
+
+// A 64-bit word at a wave-uniform address that no lane of the running launch
+// writes (syndrome bits, decision bits of the previous iteration): read with a
+// scalar load.
+__device__ __forceinline__ uint64_t uniform_word(const uint64_t *p) {
+    typedef const __attribute__((address_space(4))) uint64_t ConstWord;
+    return *(ConstWord *)p;
+}
+
+// Workgroup-uniform pointers of one (frame, row) for rows whose split into
+// DS stored blocks followed by D - DS degree-1 blocks is a compile-time fact.
+// A thread's checks are a0 + 256 q; the wave's 64 checks of step q are bit
+// positions 0..63 of word w0 + 4 q of every packed bit array of the row, so
+// syndrome and decision bits are whole uniform words, one bit per lane.
+template <int D, int DS, typename Msg>
+struct FixedRow {
+    const float *tot[D];        // stored k: totals row of the block's column, advanced by its shift
+    Msg *msg[D];                // stored k: the block's messages
+    const float *psi[D];        // degree-1 k: Psi of the block's variables, check order
+    const uint64_t *dprev[D];   // degree-1 k: decision words of iteration t-1
+    uint64_t *dcur[D];          // degree-1 k: decision words of iteration t
+    const float *llr[D];        // degree-1 k: channel LLRs of the block's column (posteriors only)
+    float *post[D];             // degree-1 k: posteriors of iteration t, or null
+    unsigned shift[D];
+    const uint64_t *syn;        // the row's packed syndrome words
+    unsigned Z, Wm1;
+};
+
+// The row at row_list position y, from its descriptor: one burst of scalar
+// loads, independent of every other table.
+template <int D, int DS, typename Msg>
+__device__ __forceinline__ FixedRow<D, DS, Msg> fixed_row(const CodeDev &c, const CnArgs &A, int f,
+                                                          int y) {
+    FixedRow<D, DS, Msg> R;
+    const unsigned Z = (unsigned)c.Z;
+    R.Z = Z;
+    R.Wm1 = (unsigned)c.W - 1;
+    const int32_t *d = c.row_desc + (size_t)y * kRowDescWords;
+    const float *tot = A.tot + (size_t)f * A.tot_frame;
+    Msg *msg = reinterpret_cast<Msg *>(A.msg) + (size_t)f * A.msg_frame;
+    R.syn = A.synbits + (size_t)f * A.syn_frame + (unsigned)d[16];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (k < DS) {
+            R.tot[k] = tot + (unsigned)d[k];
+            R.msg[k] = msg + (unsigned)d[6 + k];
+        } else {
+            R.psi[k] = A.psi + (size_t)f * A.psi_frame + (unsigned)d[12];
+            R.dprev[k] = A.d1_prev + (size_t)f * A.d1_frame + (unsigned)d[13];
+            R.dcur[k] = A.d1_cur ? A.d1_cur + (size_t)f * A.d1_frame + (unsigned)d[13] : nullptr;
+            R.llr[k] = A.llr + (size_t)f * c.n + (unsigned)d[14];
+            R.shift[k] = (unsigned)d[15];
+            R.post[k] = A.d1post ? A.d1post + (size_t)f * A.psi_frame + (unsigned)d[12] : nullptr;
+        }
+    }
+    return R;
+}
+
+// K checks a + 256 q (q < K) of a fixed row; w = the wave's word of check a.
+// Padding lanes (check >= Z) read in-bounds slack (the row stride of the
+// totals and the padding after the message and Psi regions cover them), are
+// masked out of the vote and the decision words, and store nothing.  Returns
+// true if one of this thread's checks fails the parity check of the voted
+// iteration.
+template <int D, int DS, int K, int MODE, typename Msg>
+__device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const CnArgs &A,
+                                            unsigned a, unsigned w, const PhiConsts &PK,
+                                            bool skip, bool &skipped) {
+    float lt[K][D];  // stored k: totals of iteration t-1; degree-1 k: Psi
+    float mo[K][D];  // stored k: messages of iteration t-1
+    uint64_t sw[K];  // syndrome words
+    uint64_t dw[K][D];  // degree-1 k: decision words of iteration t-1
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const unsigned wq = min(w + 4u * q, R.Wm1);
+        sw[q] = uniform_word(R.syn + wq);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (k < DS) {
+                lt[q][k] = at(R.tot[k] + q * kBlock, a);
+                mo[q][k] = (base_mode(MODE) == kSteady) ? msg_load<Msg>(&at(R.msg[k] + q * kBlock, a))
+                                                        : 0.0f;
+            } else {
+                lt[q][k] = at(R.psi[k] + q * kBlock, a);
+                if (base_mode(MODE) != kFirst) dw[q][k] = uniform_word(R.dprev[k] + wq);
+            }
+        }
+    }
+    // Every load above is issued before the frame-skip test, whose flag load
+    // then overlaps them (the empty asm keeps the loads on this side of it).
+    asm volatile("" ::: "memory");
+    if (skip) {
+        skipped = true;
+        return false;
+    }
+    float x[K][D];  // inputs L_vc of iteration t-1 (degree-1: Psi)
+    bool dec[K][D]; // decisions of the voted iteration
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (k < DS) {
+                x[q][k] = lt[q][k] - mo[q][k];
+                dec[q][k] = lt[q][k] < 0.0f;
+            } else {
+                x[q][k] = lt[q][k];
+                if (base_mode(MODE) == kFirst)
+                    dec[q][k] = x[q][k] < 0.0f;
+                else if (base_mode(MODE) == kVoteOnly && A.d1_from_llr)
+                    dec[q][k] = x[q][k] < 0.0f;
+                else
+                    dec[q][k] = lane_bit(dw[q][k]);
+            }
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        bool par = lane_bit(sw[q]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) par ^= dec[q][k];
+        bad |= par && (a + q * kBlock < R.Z);
+    }
+    if (base_mode(MODE) == kVoteOnly) return bad;
+
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const unsigned aq = a + q * kBlock;
+        const bool valid = aq < R.Z;
+        // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
+        float ph[D];
+        bool neg[D];
+        bool par = lane_bit(sw[q]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            neg[k] = x[q][k] < 0.0f;
+            par ^= neg[k];
+            ph[k] = (k < DS) ? phi_f32(fabsf(x[q][k]), PK) : fabsf(x[q][k]);
+        }
+        float ex[D];
+        if constexpr (D == 1) {
+            ex[0] = 0.0f;
+        } else {
+            float pre[D];
+            pre[0] = 0.0f;
+#pragma unroll
+            for (int k = 1; k < D; ++k) pre[k] = (k == 1) ? ph[0] : pre[k - 1] + ph[k - 1];
+            float suf = ph[D - 1];
+            ex[D - 1] = pre[D - 1];
+#pragma unroll
+            for (int k = D - 2; k >= 0; --k) {
+                ex[k] = (k == 0) ? suf : pre[k] + suf;
+                suf += ph[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const bool sgn = par ^ neg[k];  // the message to block k is negative
+            if (k < DS) {
+                const float mag = phi_f32(ex[k], PK);
+                if (valid) msg_store<Msg>(&at(R.msg[k] + q * kBlock, a), sgn ? -mag : mag);
+            } else {
+                // decision of the degree-1 variable: sign of Q + m, decided in
+                // the Phi domain (|Q| > |m| exactly when Phi(|Q|) < S).  The
+                // signs of Q and m differ exactly when the check's whole sign
+                // parity `par` is odd; then the larger magnitude decides.
+                const float S = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, kPhiHi);
+                const bool d = neg[k] ^ (par && !(ph[k] < S));
+                const unsigned long long bits = wave_ballot(valid && d);
+                if ((threadIdx.x & 63) == 0 && valid) at(R.dcur[k], w + 4u * q) = bits;
+                if constexpr (with_post(MODE)) {
+                    if (valid) {
+                        unsigned j = aq + R.shift[k];
+                        j -= (j >= R.Z) ? R.Z : 0u;
+                        const float mag = phi_f32(ex[k], PK);
+                        at(R.post[k], aq) = at(R.llr[k], j) + (sgn ? -mag : mag);
+                    }
+                }
+            }
+        }
+    }
+    return bad;
+}
+
+// How many of a thread's checks of a fixed row are processed at once (bounded
+// by registers for larger rows).
+template <int D> struct FixedChunk { static constexpr int value = D <= 3 ? 4 : (D <= 6 ? 2 : 1); };
+
+// The flag of the iteration a check-pass launch votes.
+template <int MODE>
+__device__ __forceinline__ int32_t *vote_flag(const CnArgs &A, int f) {
+    return A.fail + (size_t)(base_mode(MODE) == kVoteOnly ? A.t : A.t - 1) * A.F + f;
+}
+
+// One flag per frame and iteration, set by any wave holding an unsatisfied
+// check.  Every writer stores the same value, so plain stores suffice; waves
+// that found the flag already set when their launch began store nothing.
+__device__ __forceinline__ void vote_store(int32_t *flag, int32_t seen, bool bad) {
+    const bool wave_bad = wave_ballot(bad) != 0ull;
+    if (wave_bad && seen == 0 && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+// A common row at row_list position y, (degree, stored blocks) known at
+// compile time.  The frame-skip flag, the vote flag and the row descriptor
+// are independent scalar loads; the frame is skipped (its earlier check
+// succeeded) only after they are issued.
 template <int D, int DS, int MODE, typename Msg, int CPT>
-__device__ __forceinline__ void check_row(const CodeDev &c, const CnArgs &A, int f, int r,
-                                          unsigned tile) {
+__device__ __forceinline__ void check_row_fixed(const CodeDev &c, const CnArgs &A, int f, int y,
+                                                unsigned tile) {
+    const FixedRow<D, DS, Msg> R = fixed_row<D, DS, Msg>(c, A, f, y);
+    int32_t *flag = vote_flag<MODE>(A, f);
+    // both flag loads are unconditional (in bounds either way), so that they
+    // issue together with the descriptor loads
+    const int32_t seen = A.vote ? *flag : 1;
+    const int32_t prev = A.fail[(size_t)max(A.skip_after, 0) * A.F + f];
+    const bool skip = A.skip_after >= 0 && prev == 0;
+    constexpr int K = FixedChunk<D>::value < CPT ? FixedChunk<D>::value : CPT;
+    const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned a0 = tile * (kBlock * CPT) + threadIdx.x;
+    const unsigned w0 = tile * (4u * CPT) + wave;
+    const PhiConsts PK = phi_consts();
+    bool bad = false, skipped = false;
+#pragma unroll
+    for (int q0 = 0; q0 < CPT; q0 += K) {
+        bad |= fixed_chunk<D, DS, K, MODE, Msg>(R, A, a0 + q0 * kBlock, w0 + 4u * q0, PK, skip,
+                                                skipped);
+        if (skipped) return;
+    }
+    if (A.vote) vote_store(flag, seen, bad);
+}
+
+// Any other row (base row r), degree D known at compile time.
+template <int D, int MODE, typename Msg, int CPT>
+__device__ __forceinline__ void check_row_generic(const CodeDev &c, const CnArgs &A, int f, int r,
+                                                  unsigned tile) {
+    if (A.skip_after >= 0 && A.fail[(size_t)A.skip_after * A.F + f] == 0) return;
+    int32_t *flag = vote_flag<MODE>(A, f);
+    const int32_t seen = A.vote ? *flag : 1;
     const RowCtx<D, Msg> R = load_row<D, Msg>(c, A, f, r);
     constexpr int K = ChunkOf<D>::value < CPT ? ChunkOf<D>::value : CPT;
     const unsigned a0 = tile * (kBlock * CPT) + threadIdx.x;
     int bad = 0;
 #pragma unroll
     for (int q0 = 0; q0 < CPT; q0 += K)
-        bad |= check_chunk<D, DS, K, MODE, Msg>(R, A, a0 + q0 * kBlock);
-    if (A.vote) {
-        // One flag per frame and iteration, set by any workgroup holding an
-        // unsatisfied check.  Every writer stores the same value, so plain
-        // stores suffice; reading first keeps all but a few workgroups per
-        // frame from storing at all (the next launch sees the stores).
-        bad = __syncthreads_or(bad);
-        if (bad && threadIdx.x == 0) {
-            int32_t *flag = A.fail + (size_t)(MODE == kVoteOnly ? A.t : A.t - 1) * A.F + f;
-            if (*reinterpret_cast<volatile int32_t *>(flag) == 0) *flag = 1;
-        }
-    }
+        bad |= check_chunk<D, -1, K, MODE, Msg>(R, A, a0 + q0 * kBlock);
+    if (A.vote) vote_store(flag, seen, bad != 0);
 }
 
-// Check update of one (frame, row, tile) work item: dispatch on the row's
-// degree and number of stored blocks.  The common rows (degree <= 6 with at
-// most one degree-1 block, as in multi-edge codes) are compiled for every
-// (degree, stored blocks) pair; every other row goes to the generic class,
-// compiled per degree with the split read at run time.
+// Check update of one (frame, row, tile) work item, the row at position y of
+// the row list: dispatch on the row's class.  The common rows (degree <= 6
+// with at most one degree-1 block, as in multi-edge codes) are compiled for
+// every (degree, stored blocks) class, found from y without a memory load;
+// every other row goes to the generic class, compiled per degree with the
+// split read at run time.
 template <typename Msg, bool kLarge, int MODE, int CPT>
-__device__ __forceinline__ void check_work(const CodeDev &c, const CnArgs &A, int f, int r,
+__device__ __forceinline__ void check_work(const CodeDev &c, const CnArgs &A, int f, int y,
                                            unsigned tile) {
 #define LDPC_CASE(D) \
-    case D: check_row<D, -1, MODE, Msg, CPT>(c, A, f, r, tile); break;
-#define LDPC_CASE2(D, S) \
-    case (D) * 32 + (S): check_row<D, S, MODE, Msg, CPT>(c, A, f, r, tile); break;
+    case D: check_row_generic<D, MODE, Msg, CPT>(c, A, f, r, tile); break;
+#define LDPC_CLASS(I, D, S) \
+    case I: check_row_fixed<D, S, MODE, Msg, CPT>(c, A, f, y, tile); break;
     if (!kLarge) {
-        static_assert(kSmallRowDegree == 6, "case list below covers degrees 1..6");
-        switch (c.row_deg[r] * 32 + c.row_ns[r]) {
-            LDPC_CASE2(1, 0) LDPC_CASE2(1, 1) LDPC_CASE2(2, 1) LDPC_CASE2(2, 2)
-            LDPC_CASE2(3, 2) LDPC_CASE2(3, 3) LDPC_CASE2(4, 3) LDPC_CASE2(4, 4)
-            LDPC_CASE2(5, 4) LDPC_CASE2(5, 5) LDPC_CASE2(6, 5) LDPC_CASE2(6, 6)
+        static_assert(kFixedClasses == 12, "class list below covers degrees 1..6");
+        int cls = 0;
+#pragma unroll
+        for (int i = 0; i < kFixedClasses - 1; ++i) cls += (y >= c.cls_end[i]) ? 1 : 0;
+        switch (cls) {
+            LDPC_CLASS(0, 1, 0) LDPC_CLASS(1, 1, 1) LDPC_CLASS(2, 2, 1) LDPC_CLASS(3, 2, 2)
+            LDPC_CLASS(4, 3, 2) LDPC_CLASS(5, 3, 3) LDPC_CLASS(6, 4, 3) LDPC_CLASS(7, 4, 4)
+            LDPC_CLASS(8, 5, 4) LDPC_CLASS(9, 5, 5) LDPC_CLASS(10, 6, 5) LDPC_CLASS(11, 6, 6)
             default: break;
         }
     } else {
         static_assert(LDPC_MAX_ROW_DEGREE == 16, "case list below covers degrees 1..16");
+        const int r = c.row_list[y];
         switch (c.row_deg[r]) {
             LDPC_CASE(1) LDPC_CASE(2) LDPC_CASE(3) LDPC_CASE(4) LDPC_CASE(5) LDPC_CASE(6)
             LDPC_CASE(7) LDPC_CASE(8) LDPC_CASE(9) LDPC_CASE(10) LDPC_CASE(11) LDPC_CASE(12)
@@ -319,7 +595,7 @@ __device__ __forceinline__ void check_work(const CodeDev &c, const CnArgs &A, in
         }
     }
 #undef LDPC_CASE
-#undef LDPC_CASE2
+#undef LDPC_CLASS
 }
 
 struct VnArgs {
@@ -363,12 +639,14 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
             const int i = i0 + min(b + u, deg - 1);
             const unsigned s = (unsigned)c.core_shift[i];
             const unsigned idx = (j >= s) ? j - s : j + Z - s;
-            v[u] = msg_load<Msg>(&at(msg, (unsigned)c.core_state[i] * Z + idx));
+            v[u] = msg_load<Msg>(&at(msg, (unsigned)c.core_state[i] * (unsigned)c.Zp + idx));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) L += (b + u < deg) ? v[u] : 0.0f;
     }
-    at(A.tot + (size_t)f * A.tot_frame, (unsigned)k * Z + j) = L;
+    float *row = A.tot + (size_t)f * A.tot_frame + (size_t)k * c.Zt;
+    at(row, j) = L;
+    at(row, j + Z) = L;
 }
 
 // Pack the syndrome bytes into 64-bit words per base row: bit a%64 of word a/64.
@@ -383,13 +661,15 @@ __device__ __forceinline__ void pack_syndrome_work(const CodeDev &c, const uint8
         synbits[(size_t)f * syn_frame + (size_t)r * c.W + (a >> 6)] = bits;
 }
 
-// Core totals of iteration 0: L_v = Q_v.
+// Core totals of iteration 0: L_v = Q_v (both copies of the row).
 __device__ __forceinline__ void init_totals_work(const CodeDev &c, const float *llr, float *tot,
                                                  size_t tot_frame, int f, int k, unsigned tile) {
     const int j = tile * kBlock + threadIdx.x;
     if (j >= c.Z) return;
-    tot[(size_t)f * tot_frame + (size_t)k * c.Z + j] =
-        llr[(size_t)f * c.n + (size_t)c.core_col[k] * c.Z + j];
+    const float q = llr[(size_t)f * c.n + (size_t)c.core_col[k] * c.Z + j];
+    float *row = tot + (size_t)f * tot_frame + (size_t)k * c.Zt;
+    row[j] = q;
+    row[j + c.Z] = q;
 }
 
 // Degree-1 inputs in check order: Psi[a] = +-Phi(|Q_p|), p the variable of
@@ -403,7 +683,7 @@ __device__ __forceinline__ void init_psi_work(const CodeDev &c, const float *llr
     j -= (j >= Z) ? Z : 0u;
     const float q = llr[(size_t)f * c.n + (size_t)c.d1_col[k] * Z + j];
     const float p = phi_f32(fabsf(q));
-    psi[(size_t)f * psi_frame + (size_t)k * Z + a] = q < 0.0f ? -p : p;
+    psi[(size_t)f * psi_frame + (size_t)k * c.Zp + a] = q < 0.0f ? -p : p;
 }
 
 struct FinArgs {
@@ -457,14 +737,14 @@ __device__ __forceinline__ void finalize_work(const CodeDev &c, const FinArgs &A
     float L = q;
     int bit = q < 0.0f;
     if (kind == COL_CORE) {
-        L = A.tot[(size_t)f * A.tot_frame + (size_t)ref * Z + j];
+        L = A.tot[(size_t)f * A.tot_frame + (size_t)ref * c.Zt + j];
         bit = L < 0.0f;
     } else if (kind == COL_DEG1 && it > 0) {
         int a = j - c.d1_shift[ref];
         a += (a < 0) ? Z : 0;
         const uint64_t wd = A.d1bits[it & 1][(size_t)f * A.d1_frame + (size_t)ref * c.W + (a >> 6)];
         bit = (int)((wd >> (a & 63)) & 1ull);
-        if (A.llr_out) L = A.d1post[it & 1][(size_t)f * A.psi_frame + (size_t)ref * Z + a];
+        if (A.llr_out) L = A.d1post[it & 1][(size_t)f * A.psi_frame + (size_t)ref * c.Zp + a];
     }
     A.bits_out[(size_t)f * c.n + v] = (uint8_t)bit;
     if (A.llr_out) A.llr_out[(size_t)f * c.n + v] = L;
