@@ -40,7 +40,7 @@ PAPER_KRAW_MBPS = 1.72       # GTX 1080, q=21 QC code, Table II (context only)
 # fingerprint differ and the figure is reported as null.
 KERNEL_SOURCES = ("internal.h", "passes.h", "decoder.hip")
 MEASURED_TRAFFIC = {
-    "check_pass": {"sources": "4d2d3a67a15beeed", "fetch_kib": 55618.5, "write_kib": 65388.4,
+    "check_pass": {"sources": "eebb5cff0a23eb82", "fetch_kib": 50781.5, "write_kib": 64746.3,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
@@ -117,8 +117,9 @@ def run_decodes(torch, code, dQ, ds, T, steps, warmup, fp16, F):
 
 def kernel_roofline(torch, code, dQ, ds, T, steps, F, info):
     """Average durations of the check and variable passes from HIP events
-    recorded on the decode stream around every launch, over `steps` decodes."""
-    ev = HipEvents(2 * T + 1)
+    that the launches record at the start and end of every kernel (on the
+    decode stream), over `steps` decodes."""
+    ev = HipEvents(4 * T)
     ws = code.alloc_workspace(F, T)
     out = (torch.empty((F, code.n), dtype=torch.uint8, device="cuda"),
            torch.empty(F, dtype=torch.int32, device="cuda"),
@@ -129,8 +130,8 @@ def kernel_roofline(torch, code, dQ, ds, T, steps, F, info):
         code.decode(dQ, ds, T, workspace=ws, out=out, timing_events=ev.arr)
         torch.cuda.synchronize()
         for t in range(1, T + 1):
-            cn_ms[t - 1] += ev.elapsed_ms(2 * (t - 1), 2 * (t - 1) + 1)
-            vn_ms[t - 1] += ev.elapsed_ms(2 * (t - 1) + 1, 2 * t)
+            cn_ms[t - 1] += ev.elapsed_ms(4 * (t - 1), 4 * (t - 1) + 1)
+            vn_ms[t - 1] += ev.elapsed_ms(4 * (t - 1) + 2, 4 * (t - 1) + 3)
     ev.close()
     iters = out[1].cpu().numpy()
     cn_ms /= steps

@@ -105,11 +105,12 @@ typedef struct {
                                 depend on it                                      */
     float *llr_out;          /* optional device [F][n]: posterior L_v at exit      */
     void **timing_events;    /* optional host array of caller-created hipEvent_t
-                                handles, recorded on the decode stream around the
-                                iteration kernels: event 2(t-1) before the check
-                                pass of iteration t, 2(t-1)+1 before its variable
-                                pass, 2T after the last variable pass             */
-    int32_t n_timing_events; /* >= 2*max_iters + 1 when timing_events is set      */
+                                handles, recorded by the launches of the iteration
+                                kernels themselves (start and end of execution):
+                                events 4(t-1), 4(t-1)+1 at the start and end of the
+                                check pass of iteration t, 4(t-1)+2, 4(t-1)+3 at
+                                the start and end of its variable pass            */
+    int32_t n_timing_events; /* >= 4*max_iters when timing_events is set          */
 } ldpc_decode_opts;
 
 /* Fill opts with the defaults {early_stop=1, check_from_iter=0, msg_fp16=0,

@@ -241,6 +241,17 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         dd[17] = r;
     }
     const size_t o_rd = put(row_desc);
+    // per core column: (message offset, shift) of its blocks at a fixed stride
+    int max_cd = 1;
+    for (int k = 0; k < NC; ++k) max_cd = std::max(max_cd, core_deg[k]);
+    const int tab_stride = 2 * max_cd;
+    std::vector<int32_t> core_tab((size_t)std::max(NC, 1) * tab_stride, 0);
+    for (int k = 0; k < NC; ++k)
+        for (int i = 0; i < core_deg[k]; ++i) {
+            core_tab[(size_t)k * tab_stride + 2 * i] = core_state[core_first[k] + i] * Zp;
+            core_tab[(size_t)k * tab_stride + 2 * i + 1] = core_shift[core_first[k] + i];
+        }
+    const size_t o_ct = put(core_tab);
 
     ldpc_code *code = new (std::nothrow) ldpc_code();
     if (!code) return fail_with(LDPC_ENOMEM, "host allocation failed");
@@ -294,6 +305,8 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.core_deg = T + o_cd;
     d.core_state = T + o_cs;
     d.core_shift = T + o_csh;
+    d.core_tab = T + o_ct;
+    d.core_tab_stride = tab_stride;
     d.col_kind = T + o_colk;
     d.col_ref = T + o_colr;
     d.d1_shift = T + o_d1s;
@@ -354,9 +367,9 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const 
         return fail_with(LDPC_EINVAL, "checks_per_thread = %d is not 0, 1, 2 or 4",
                          o.checks_per_thread);
     if (o.check_from_iter < 0) return fail_with(LDPC_EINVAL, "check_from_iter < 0");
-    if (o.timing_events && o.n_timing_events < 2 * max_iters + 1)
-        return fail_with(LDPC_EINVAL, "%d timing events; need 2*max_iters + 1 = %d",
-                         o.n_timing_events, 2 * max_iters + 1);
+    if (o.timing_events && (int64_t)o.n_timing_events < 4ll * max_iters)
+        return fail_with(LDPC_EINVAL, "%d timing events; need 4*max_iters = %lld",
+                         o.n_timing_events, 4ll * max_iters);
     if ((int64_t)(max_iters + 1) * F >= (1ll << 31))
         return fail_with(LDPC_EINVAL, "(max_iters + 1) * F too large");
     const size_t need = ldpc::work_layout(code->dev, F, max_iters, o.msg_fp16 != 0,

@@ -34,6 +34,8 @@
 // plus a 32-bit lane offset, so loads and stores use the scalar-base form.
 #include "passes.h"
 
+#include <hip/hip_ext.h>
+
 namespace ldpc {
 
 namespace {
@@ -56,27 +58,43 @@ __global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, unsign
 
 // Common rows run with the requested checks per thread (1, 2 or 4); the rare
 // generic rows, and launches that also write posteriors, with the default.
+// A launch of 256-thread workgroups, optionally recording caller events at
+// the start and end of the kernel's execution.
+template <typename... KArgs, typename... Args>
+void launch_timed(void (*kernel)(KArgs...), dim3 grid, hipStream_t st, hipEvent_t start,
+                  hipEvent_t stop, Args... args) {
+    if (start || stop)
+        hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, start, stop, 0, args...);
+    else
+        kernel<<<grid, dim3(kBlock), 0, st>>>(args...);
+}
+
 template <typename Msg, int MODE>
-void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, int cpt, hipStream_t st) {
+void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, int cpt, hipStream_t st,
+                       hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
+    const bool both = c.n_small > 0 && c.n_large > 0;
     if (c.n_small > 0) {
         if constexpr (with_post(MODE)) cpt = kDefaultChecksPerThread;
         const unsigned tl = check_tiles(c.Z, cpt), rows = (unsigned)c.n_small;
         const dim3 g(xcd_grid(tl * rows * (unsigned)F));
+        hipEvent_t e1 = both ? nullptr : stop;
         if constexpr (with_post(MODE)) {
-            check_pass<Msg, false, MODE, kDefaultChecksPerThread><<<g, dim3(kBlock), 0, st>>>(c, a, tl, rows);
+            launch_timed(check_pass<Msg, false, MODE, kDefaultChecksPerThread>, g, st, start, e1, c, a,
+                         tl, rows);
         } else {
             if (cpt == 1)
-                check_pass<Msg, false, MODE, 1><<<g, dim3(kBlock), 0, st>>>(c, a, tl, rows);
+                launch_timed(check_pass<Msg, false, MODE, 1>, g, st, start, e1, c, a, tl, rows);
             else if (cpt == 2)
-                check_pass<Msg, false, MODE, 2><<<g, dim3(kBlock), 0, st>>>(c, a, tl, rows);
+                launch_timed(check_pass<Msg, false, MODE, 2>, g, st, start, e1, c, a, tl, rows);
             else
-                check_pass<Msg, false, MODE, 4><<<g, dim3(kBlock), 0, st>>>(c, a, tl, rows);
+                launch_timed(check_pass<Msg, false, MODE, 4>, g, st, start, e1, c, a, tl, rows);
         }
     }
     if (c.n_large > 0) {
         const unsigned tl = check_tiles(c.Z, kDefaultChecksPerThread), rows = (unsigned)c.n_large;
-        check_pass<Msg, true, MODE, kDefaultChecksPerThread>
-            <<<dim3(xcd_grid(tl * rows * (unsigned)F)), dim3(kBlock), 0, st>>>(c, a, tl, rows);
+        launch_timed(check_pass<Msg, true, MODE, kDefaultChecksPerThread>,
+                     dim3(xcd_grid(tl * rows * (unsigned)F)), st, both ? nullptr : start, stop, c,
+                     a, tl, rows);
     }
 }
 
@@ -96,17 +114,18 @@ __global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A, uns
 // batches flood the memory pipeline, padded slots cost real loads), sized so
 // that they divide the column degree with little padding, e.g. 3 x 17 for 51.
 template <typename Msg>
-void launch_variable_pass(const CodeDev &c, const VnArgs &v, int F, hipStream_t st) {
+void launch_variable_pass(const CodeDev &c, const VnArgs &v, int F, hipStream_t st,
+                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
     const int u = variable_batch(c.max_core_deg);
     const unsigned tl = (unsigned)((c.Z + kBlock - 1) / kBlock);
-    const dim3 grid(xcd_grid(tl * (unsigned)c.NC * (unsigned)F)), b(kBlock);
+    const dim3 g(xcd_grid(tl * (unsigned)c.NC * (unsigned)F));
     switch (u) {
-        case 8: variable_pass<8, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
-        case 11: variable_pass<11, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
-        case 16: variable_pass<16, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
-        case 17: variable_pass<17, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
-        case 21: variable_pass<21, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
-        default: variable_pass<26, Msg><<<grid, b, 0, st>>>(c, v, tl); break;
+        case 8: launch_timed(variable_pass<8, Msg>, g, st, start, stop, c, v, tl); break;
+        case 11: launch_timed(variable_pass<11, Msg>, g, st, start, stop, c, v, tl); break;
+        case 16: launch_timed(variable_pass<16, Msg>, g, st, start, stop, c, v, tl); break;
+        case 17: launch_timed(variable_pass<17, Msg>, g, st, start, stop, c, v, tl); break;
+        case 21: launch_timed(variable_pass<21, Msg>, g, st, start, stop, c, v, tl); break;
+        default: launch_timed(variable_pass<26, Msg>, g, st, start, stop, c, v, tl); break;
     }
 }
 
@@ -221,25 +240,27 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
         a.d1_cur = d1b[t & 1];
         a.d1post = d1p[t & 1];
         a.skip_after = t >= 2 ? t - 2 : -1;
-        if (l.events) (void)hipEventRecord(l.events[2 * (t - 1)], st);
+        hipEvent_t *ev = l.events ? l.events + 4 * (t - 1) : nullptr;
+        hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
         if (t == 1) {
             if (a.d1post)
-                launch_check_pass<Msg, kFirst | kPost>(c, a, F, l.cpt, st);
+                launch_check_pass<Msg, kFirst | kPost>(c, a, F, l.cpt, st, e0, e1);
             else
-                launch_check_pass<Msg, kFirst>(c, a, F, l.cpt, st);
+                launch_check_pass<Msg, kFirst>(c, a, F, l.cpt, st, e0, e1);
         } else {
             if (a.d1post)
-                launch_check_pass<Msg, kSteady | kPost>(c, a, F, l.cpt, st);
+                launch_check_pass<Msg, kSteady | kPost>(c, a, F, l.cpt, st, e0, e1);
             else
-                launch_check_pass<Msg, kSteady>(c, a, F, l.cpt, st);
+                launch_check_pass<Msg, kSteady>(c, a, F, l.cpt, st, e0, e1);
         }
-        if (l.events) (void)hipEventRecord(l.events[2 * (t - 1) + 1], st);
         if (c.NC > 0) {
             v.t = t;
-            launch_variable_pass<Msg>(c, v, F, st);
+            launch_variable_pass<Msg>(c, v, F, st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+        } else if (ev) {
+            (void)hipEventRecord(ev[2], st);
+            (void)hipEventRecord(ev[3], st);
         }
     }
-    if (l.events) (void)hipEventRecord(l.events[2 * T], st);
     // the check of the last iteration (or of the channel decisions when T = 0)
     a.t = T;
     a.vote = 1;

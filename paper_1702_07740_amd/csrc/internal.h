@@ -82,6 +82,11 @@ struct CodeDev {
     // core_state[core_first[k] + i], core_shift[...], i < core_deg[k], in
     // increasing row order
     const int32_t *core_col, *core_first, *core_deg, *core_state, *core_shift;
+    // the same blocks as (message offset state * Zp, shift) pairs, column k at
+    // core_tab[k * core_tab_stride], so a column's entries are addressed
+    // without loading core_first first
+    const int32_t *core_tab;
+    int32_t core_tab_stride;
     int32_t max_core_deg;  // largest degree of a core column
     // per base column: kind and index within its kind
     const int32_t *col_kind, *col_ref;
@@ -113,7 +118,7 @@ struct DecodeLaunch {
     uint8_t *conv_out;
     float *llr_out;
     char *ws;
-    hipEvent_t *events;    // optional: 2T + 1 caller events around the iteration kernels
+    hipEvent_t *events;    // optional: 4T caller events, start and end of each iteration kernel
     hipStream_t stream;
 };
 

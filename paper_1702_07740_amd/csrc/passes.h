@@ -25,25 +25,30 @@ __device__ __forceinline__ unsigned xcd_item(unsigned g, unsigned n) {
     const unsigned per = (n + kXcds - 1) / kXcds;
     return (g % kXcds) * per + g / kXcds;
 }
-constexpr float kPhiLo = 1e-7f;
-constexpr float kPhiHi = 30.0f;
+// Units.  On the device every log-likelihood ratio of the decoding state
+// (core totals, messages, degree-1 inputs) is held in base 2: b = L log2(e),
+// the natural-log value L scaled by 1/ln 2.  Channel LLRs come in and
+// posteriors go out in natural units.  In base 2 the exponential inside Phi is
+// a bare exp2 and Phi keeps its involution form, so one function serves
+// both directions of the check update.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+// The clamp [1e-7, 30] of Phi's argument, in base-2 units.
+constexpr float kPhiLo = 1.442695066e-07f;
+constexpr float kPhiHi = 4.328084946e+01f;
 
-// Phi(x) = -ln tanh(x/2) on the clamped argument [1e-7, 30], branch-free:
-//   x <  2.25: Phi(x) = ln 2 - ln x + g(x^2/4), where g(u) = -ln(tanh(y)/y),
-//              y = sqrt(u), is smooth and even; g(w/4) = w H(w) with H a
-//              degree-5 near-minimax fit on w in [0, 5.07) (relative error of
-//              the fit below 8e-8 of Phi);
-//   x >= 2.25: Phi(x) = 2 atanh(t), t = e^{-x} <= 0.106, by its odd series to
-//              t^5 (truncation below 2e-7 relative; no cancellation for large x).
-// Both branches use one hardware transcendental (log2 or exp2).  Relative
-// error in FP32 below 1e-6 for x < 20 and below 2e-6 up to 30 (there
-// Phi < 2e-9).
-// The polynomial coefficients that cannot ride in an instruction's literal
-// field (an FMA takes one literal), held in registers for a whole launch.
-// Each is passed through an empty asm statement once, so the compiler keeps
-// it in a register instead of re-materialising it before every use.
+// Phi in base-2 units: phi2(b) = log2(e) Phi(b ln 2), where Phi(x) =
+// -ln tanh(x/2); like Phi it is a decreasing involution.  Argument clamped to
+// [kPhiLo, kPhiHi] (the natural-unit clamp [1e-7, 30]).  Branch-free:
+//   b <  1.5 log2(e): phi2(b) = 1 - log2(ln 2) - log2(b) + w H(w), w = b^2,
+//                     H a degree-3 near-minimax fit of the smooth remainder
+//                     (the expansion of -ln(tanh(y)/y) about 0, rescaled);
+//   b >= 1.5 log2(e): phi2(b) = log2(e) 2 atanh(t), t = 2^-b = e^-x, by its
+//                     odd series to t^7 (t <= 0.223; truncation below 4e-7).
+// Each branch takes one hardware transcendental (log2 or exp2).  Relative
+// error in FP32 below 1e-6 over the whole clamped range.
 struct PhiConsts {
-    float h5, h4, h3, h2, h1, h0, ln2, q1, hi;
+    float h3, h2, h1, h0, a, p3, p2, p1, p0, hi;  // polynomial coefficients, clamp bound
 };
 
 __device__ __forceinline__ float opaque(float v) {
@@ -51,39 +56,41 @@ __device__ __forceinline__ float opaque(float v) {
     return v;
 }
 
+// The constants an FMA cannot take as its one literal, held in registers for
+// a whole launch: each passes through an empty asm statement once, so the
+// compiler keeps it instead of re-materialising it before every use.
 __device__ __forceinline__ PhiConsts phi_consts() {
     PhiConsts K;
-    K.h5 = opaque(-4.600071435e-08f);
-    K.h4 = opaque(1.415273005e-06f);
-    K.h3 = opaque(-2.400134144e-05f);
-    K.h2 = opaque(3.378146503e-04f);
-    K.h1 = opaque(-4.857770633e-03f);
-    K.h0 = opaque(8.333229274e-02f);
-    K.ln2 = opaque(0.6931471805599453f);
-    K.q1 = opaque(2.0f / 3.0f);
+    K.h3 = opaque(-1.304959028e-06f);
+    K.h2 = opaque(5.194569894e-05f);
+    K.h1 = opaque(-1.614399021e-03f);
+    K.h0 = opaque(5.775980651e-02f);
+    K.a = opaque(1.528766394e+00f);
+    K.p3 = opaque(4.121985734e-01f);
+    K.p2 = opaque(5.770780444e-01f);
+    K.p1 = opaque(9.617967010e-01f);
+    K.p0 = opaque(2.885390043e+00f);
     K.hi = opaque(kPhiHi);
     return K;
 }
 
-__device__ __forceinline__ float phi_f32(float x, const PhiConsts &K) {
-    constexpr float kLog2e = 1.4426950408889634f;
-    constexpr float kLn2 = 0.6931471805599453f;
-    x = __builtin_amdgcn_fmed3f(x, kPhiLo, K.hi);
-    const float w = x * x;
-    float h = fmaf(w, K.h5, K.h4);
-    h = fmaf(h, w, K.h3);
-    h = fmaf(h, w, K.h2);
+__device__ __forceinline__ float phi2(float b, const PhiConsts &K) {
+    b = __builtin_amdgcn_fmed3f(b, kPhiLo, K.hi);
+    const float w = b * b;
+    float h = fmaf(w, K.h3, K.h2);
     h = fmaf(h, w, K.h1);
     h = fmaf(h, w, K.h0);
-    const float small = fmaf(-kLn2, __builtin_amdgcn_logf(x), fmaf(h, w, K.ln2));
-    const float t = __builtin_amdgcn_exp2f(-x * kLog2e);
+    const float small = fmaf(h, w, K.a) - __builtin_amdgcn_logf(b);
+    const float t = __builtin_amdgcn_exp2f(-b);
     const float t2 = t * t;
-    const float p = fmaf(t2, fmaf(t2, 2.0f / 5.0f, K.q1), 2.0f);
+    float p = fmaf(t2, K.p3, K.p2);
+    p = fmaf(t2, p, K.p1);
+    p = fmaf(t2, p, K.p0);
     const float large = t * p;
-    return x < 2.25f ? small : large;
+    return b < 2.164042473e+00f ? small : large;
 }
 
-__device__ __forceinline__ float phi_f32(float x) { return phi_f32(x, phi_consts()); }
+__device__ __forceinline__ float phi2(float b) { return phi2(b, phi_consts()); }
 
 template <typename Msg> __device__ __forceinline__ float msg_load(const Msg *p);
 template <> __device__ __forceinline__ float msg_load<float>(const float *p) { return *p; }
@@ -269,7 +276,7 @@ __device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs
             const int nk = x[q][k] < 0.0f;
             neg |= nk << k;
             par ^= nk;
-            ph[k] = stored<DS>(R, k) ? phi_f32(fabsf(x[q][k])) : fabsf(x[q][k]);
+            ph[k] = stored<DS>(R, k) ? phi2(fabsf(x[q][k])) : fabsf(x[q][k]);
         }
         float pre[D];
         pre[0] = 0.0f;
@@ -286,7 +293,7 @@ __device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs
         for (int k = 0; k < D; ++k) {
             const int sgn = (par ^ (neg >> k)) & 1;  // 1: the message to block k is negative
             if (stored<DS>(R, k)) {
-                const float mag = phi_f32(ex[k]);
+                const float mag = phi2(ex[k]);
                 if (valid) msg_store<Msg>(&at(R.msg, R.off[k] + a), sgn ? -mag : mag);
             } else {
                 // decision of the degree-1 variable: sign of Q + m
@@ -298,7 +305,7 @@ __device__ __forceinline__ int check_chunk(const RowCtx<D, Msg> &R, const CnArgs
                 if (with_post(MODE) && R.d1post && valid) {
                     unsigned j = a + R.shift[k];
                     j -= (j >= Z) ? Z : 0u;
-                    const float mag = phi_f32(ex[k]);
+                    const float mag = phi2(ex[k]) * kLn2;
                     at(R.d1post, R.off[k] + a) = at(R.llr, R.src[k] + j) + (sgn ? -mag : mag);
                 }
             }
@@ -449,7 +456,7 @@ __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const
         for (int k = 0; k < D; ++k) {
             neg[k] = x[q][k] < 0.0f;
             par ^= neg[k];
-            ph[k] = (k < DS) ? phi_f32(fabsf(x[q][k]), PK) : fabsf(x[q][k]);
+            ph[k] = (k < DS) ? phi2(fabsf(x[q][k]), PK) : fabsf(x[q][k]);
         }
         float ex[D];
         if constexpr (D == 1) {
@@ -471,14 +478,14 @@ __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const
         for (int k = 0; k < D; ++k) {
             const bool sgn = par ^ neg[k];  // the message to block k is negative
             if (k < DS) {
-                const float mag = phi_f32(ex[k], PK);
+                const float mag = phi2(ex[k], PK);
                 if (valid) msg_store<Msg>(&at(R.msg[k] + q * kBlock, a), sgn ? -mag : mag);
             } else {
                 // decision of the degree-1 variable: sign of Q + m, decided in
                 // the Phi domain (|Q| > |m| exactly when Phi(|Q|) < S).  The
                 // signs of Q and m differ exactly when the check's whole sign
                 // parity `par` is odd; then the larger magnitude decides.
-                const float S = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, kPhiHi);
+                const float S = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, PK.hi);
                 const bool d = neg[k] ^ (par && !(ph[k] < S));
                 const unsigned long long bits = wave_ballot(valid && d);
                 if ((threadIdx.x & 63) == 0 && valid) at(R.dcur[k], w + 4u * q) = bits;
@@ -486,7 +493,7 @@ __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const
                     if (valid) {
                         unsigned j = aq + R.shift[k];
                         j -= (j >= R.Z) ? R.Z : 0u;
-                        const float mag = phi_f32(ex[k], PK);
+                        const float mag = phi2(ex[k], PK) * kLn2;
                         at(R.post[k], aq) = at(R.llr[k], j) + (sgn ? -mag : mag);
                     }
                 }
@@ -618,7 +625,7 @@ inline int variable_batch(int max_deg) {
 }
 
 // Step 3 for the core columns: L_v = Q_v + sum of the column's messages, in
-// increasing row order.  One thread per (core column k, position j).  The
+// increasing row order (base 2: Q_v log2(e) plus the base-2 messages).  One thread per (core column k, position j).  The
 // messages are loaded U at a time with all U loads in flight together (a
 // column of degree <= U takes one batch); slots past the column's degree load
 // a clamped in-range entry and add 0.
@@ -630,16 +637,17 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
     if (j >= Z) return;
     const Msg *msg = reinterpret_cast<const Msg *>(A.msg) + (size_t)f * A.msg_frame;
     const float *llr = A.llr + (size_t)f * c.n + (size_t)c.core_col[k] * Z;
-    float L = at(llr, j);
-    const int i0 = c.core_first[k], deg = c.core_deg[k];
+    float L = at(llr, j) * kLog2e;
+    const int deg = c.core_deg[k];
+    const int32_t *tab = c.core_tab + (size_t)k * c.core_tab_stride;
     for (int b = 0; b < deg; b += U) {
         float v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = i0 + min(b + u, deg - 1);
-            const unsigned s = (unsigned)c.core_shift[i];
+            const int i = min(b + u, deg - 1);
+            const unsigned s = (unsigned)tab[2 * i + 1];
             const unsigned idx = (j >= s) ? j - s : j + Z - s;
-            v[u] = msg_load<Msg>(&at(msg, (unsigned)c.core_state[i] * (unsigned)c.Zp + idx));
+            v[u] = msg_load<Msg>(&at(msg + (unsigned)tab[2 * i], idx));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) L += (b + u < deg) ? v[u] : 0.0f;
@@ -661,19 +669,20 @@ __device__ __forceinline__ void pack_syndrome_work(const CodeDev &c, const uint8
         synbits[(size_t)f * syn_frame + (size_t)r * c.W + (a >> 6)] = bits;
 }
 
-// Core totals of iteration 0: L_v = Q_v (both copies of the row).
+// Core totals of iteration 0: L_v = Q_v, in base 2 (both copies of the row).
 __device__ __forceinline__ void init_totals_work(const CodeDev &c, const float *llr, float *tot,
                                                  size_t tot_frame, int f, int k, unsigned tile) {
     const int j = tile * kBlock + threadIdx.x;
     if (j >= c.Z) return;
-    const float q = llr[(size_t)f * c.n + (size_t)c.core_col[k] * c.Z + j];
+    const float q = llr[(size_t)f * c.n + (size_t)c.core_col[k] * c.Z + j] * kLog2e;
     float *row = tot + (size_t)f * tot_frame + (size_t)k * c.Zt;
     row[j] = q;
     row[j + c.Z] = q;
 }
 
-// Degree-1 inputs in check order: Psi[a] = +-Phi(|Q_p|), p the variable of
-// check a of degree-1 block k, with the sign of Q_p (negative iff Q_p < 0).
+// Degree-1 inputs in check order: Psi[a] = +-Phi(|Q_p|) in base 2, p the
+// variable of check a of degree-1 block k, with the sign of Q_p (negative iff
+// Q_p < 0).
 __device__ __forceinline__ void init_psi_work(const CodeDev &c, const float *llr, float *psi,
                                               size_t psi_frame, int f, int k, unsigned tile) {
     const unsigned Z = (unsigned)c.Z;
@@ -682,7 +691,7 @@ __device__ __forceinline__ void init_psi_work(const CodeDev &c, const float *llr
     unsigned j = a + (unsigned)c.d1_shift[k];
     j -= (j >= Z) ? Z : 0u;
     const float q = llr[(size_t)f * c.n + (size_t)c.d1_col[k] * Z + j];
-    const float p = phi_f32(fabsf(q));
+    const float p = phi2(fabsf(q) * kLog2e);
     psi[(size_t)f * psi_frame + (size_t)k * c.Zp + a] = q < 0.0f ? -p : p;
 }
 
@@ -737,8 +746,9 @@ __device__ __forceinline__ void finalize_work(const CodeDev &c, const FinArgs &A
     float L = q;
     int bit = q < 0.0f;
     if (kind == COL_CORE) {
-        L = A.tot[(size_t)f * A.tot_frame + (size_t)ref * c.Zt + j];
-        bit = L < 0.0f;
+        const float Lb = A.tot[(size_t)f * A.tot_frame + (size_t)ref * c.Zt + j];
+        bit = Lb < 0.0f;
+        if (it > 0) L = Lb * kLn2;  // at t = 0 the posterior is Q itself
     } else if (kind == COL_DEG1 && it > 0) {
         int a = j - c.d1_shift[ref];
         a += (a < 0) ? Z : 0;

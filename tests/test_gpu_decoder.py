@@ -299,6 +299,60 @@ def test_invalid_arguments(ldpc):
         ldpc.Code(np.zeros((1, 17), dtype=np.int32), Z)   # row degree 17 > 16
 
 
+class _HipEvents:
+    """Caller-created hipEvent_t handles through the HIP runtime torch loaded."""
+
+    def __init__(self, count):
+        import ctypes
+        self.ct = ctypes
+        self.lib = ctypes.CDLL("libamdhip64.so")
+        self.lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.arr = (ctypes.c_void_p * count)()
+        for i in range(count):
+            ev = ctypes.c_void_p()
+            assert self.lib.hipEventCreate(ctypes.byref(ev)) == 0
+            self.arr[i] = ev
+
+    def ms(self, i, j):
+        out = self.ct.c_float()
+        assert self.lib.hipEventElapsedTime(self.ct.byref(out), self.arr[i], self.arr[j]) == 0
+        return out.value
+
+    def close(self):
+        for e in self.arr:
+            self.lib.hipEventDestroy(e)
+
+
+def test_timing_events(ldpc, oracle_mod):
+    """Per-kernel events change no result, bracket each kernel in order, and
+    too short an event array is rejected."""
+    Z = 64
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    x, Q = synth.biawgn_frames(g.n, 4, -15.4, seed=21)
+    s = oracle_mod.OracleCode(base, Z).syndrome(x)
+    T = 6
+    _say("timing events", T)
+    ref = _gpu_decode(g, Q, s, T, early_stop=False)
+    ev = _HipEvents(4 * T)
+    got = _gpu_decode(g, Q, s, T, early_stop=False, timing_events=ev.arr)
+    for a, b in zip(ref[:3], got[:3]):
+        assert np.array_equal(a, b)
+    for t in range(T):
+        cn, vn = ev.ms(4 * t, 4 * t + 1), ev.ms(4 * t + 2, 4 * t + 3)
+        assert cn > 0 and vn > 0
+        assert ev.ms(4 * t + 1, 4 * t + 2) >= 0
+        if t:
+            assert ev.ms(4 * t - 1, 4 * t) >= 0
+    with pytest.raises(ldpc.LdpcError):
+        g.decode(_dev(Q), _dev(s), T, timing_events=(ev.ct.c_void_p * (4 * T - 1))())
+    torch.cuda.synchronize()
+    ev.close()
+
+
 # ------------------------------------------- full size (n = 1,000,050)
 @pytest.fixture(scope="module")
 def full_code(ldpc, oracle_mod):
