@@ -45,8 +45,8 @@ using namespace dev;
 // One launch covers the rows of one degree class; grid.y walks that class's
 // rows in the row list.
 template <typename Msg, bool kLarge, int MODE, int CPT>
-__global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, unsigned tiles,
-                                                     unsigned rows) {
+__device__ __forceinline__ void check_pass_body(const CodeDev &c, const CnArgs &A, unsigned tiles,
+                                                unsigned rows) {
     const unsigned n = tiles * rows * (unsigned)A.F;
     unsigned i = xcd_item(blockIdx.x, n);
     if (i >= n) return;
@@ -54,6 +54,18 @@ __global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, unsign
     i /= tiles;
     const int y = (kLarge ? c.n_small : 0) + (int)(i % rows);
     check_work<Msg, kLarge, MODE, CPT>(c, A, (int)(i / rows), y, tile);
+}
+
+template <typename Msg, int MODE, int CPT>
+__global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, unsigned tiles,
+                                                     unsigned rows) {
+    check_pass_body<Msg, false, MODE, CPT>(c, A, tiles, rows);
+}
+
+template <typename Msg, int MODE, int CPT>
+__global__ __launch_bounds__(kBlock) void check_pass_large(CodeDev c, CnArgs A, unsigned tiles,
+                                                           unsigned rows) {
+    check_pass_body<Msg, true, MODE, CPT>(c, A, tiles, rows);
 }
 
 // Common rows run with the requested checks per thread (1, 2 or 4); the rare
@@ -79,20 +91,20 @@ void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, int cpt, hipStr
         const dim3 g(xcd_grid(tl * rows * (unsigned)F));
         hipEvent_t e1 = both ? nullptr : stop;
         if constexpr (with_post(MODE)) {
-            launch_timed(check_pass<Msg, false, MODE, kDefaultChecksPerThread>, g, st, start, e1, c, a,
+            launch_timed(check_pass<Msg, MODE, kDefaultChecksPerThread>, g, st, start, e1, c, a,
                          tl, rows);
         } else {
             if (cpt == 1)
-                launch_timed(check_pass<Msg, false, MODE, 1>, g, st, start, e1, c, a, tl, rows);
+                launch_timed(check_pass<Msg, MODE, 1>, g, st, start, e1, c, a, tl, rows);
             else if (cpt == 2)
-                launch_timed(check_pass<Msg, false, MODE, 2>, g, st, start, e1, c, a, tl, rows);
+                launch_timed(check_pass<Msg, MODE, 2>, g, st, start, e1, c, a, tl, rows);
             else
-                launch_timed(check_pass<Msg, false, MODE, 4>, g, st, start, e1, c, a, tl, rows);
+                launch_timed(check_pass<Msg, MODE, 4>, g, st, start, e1, c, a, tl, rows);
         }
     }
     if (c.n_large > 0) {
         const unsigned tl = check_tiles(c.Z, kDefaultChecksPerThread), rows = (unsigned)c.n_large;
-        launch_timed(check_pass<Msg, true, MODE, kDefaultChecksPerThread>,
+        launch_timed(check_pass_large<Msg, MODE, kDefaultChecksPerThread>,
                      dim3(xcd_grid(tl * rows * (unsigned)F)), st, both ? nullptr : start, stop, c,
                      a, tl, rows);
     }

@@ -328,6 +328,14 @@ __device__ __forceinline__ uint64_t uniform_word(const uint64_t *p) {
     return *(ConstWord *)p;
 }
 
+// A 32-bit value at a wave-uniform address, read with a scalar load.  Used
+// for tables and flags that this launch does not write, and for the vote flag,
+// where a stale 0 only costs one redundant store of the same value.
+__device__ __forceinline__ int32_t uniform_i32(const int32_t *p) {
+    typedef const __attribute__((address_space(4))) int32_t ConstI32;
+    return *(ConstI32 *)p;
+}
+
 // Workgroup-uniform pointers of one (frame, row) for rows whose split into
 // DS stored blocks followed by D - DS degree-1 blocks is a compile-time fact.
 // A thread's checks are a0 + 256 q; the wave's 64 checks of step q are bit
@@ -345,6 +353,7 @@ struct FixedRow {
     unsigned shift[D];
     const uint64_t *syn;        // the row's packed syndrome words
     unsigned Z, Wm1;
+    int32_t any_desc;           // OR of the descriptor words read (never negative)
 };
 
 // The row at row_list position y, from its descriptor: one burst of scalar
@@ -356,16 +365,20 @@ __device__ __forceinline__ FixedRow<D, DS, Msg> fixed_row(const CodeDev &c, cons
     const unsigned Z = (unsigned)c.Z;
     R.Z = Z;
     R.Wm1 = (unsigned)c.W - 1;
-    const int32_t *d = c.row_desc + (size_t)y * kRowDescWords;
+    typedef const __attribute__((address_space(4))) int32_t ConstI32;
+    ConstI32 *d = (ConstI32 *)(c.row_desc + (size_t)y * kRowDescWords);
     const float *tot = A.tot + (size_t)f * A.tot_frame;
     Msg *msg = reinterpret_cast<Msg *>(A.msg) + (size_t)f * A.msg_frame;
     R.syn = A.synbits + (size_t)f * A.syn_frame + (unsigned)d[16];
+    R.any_desc = d[16];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         if (k < DS) {
             R.tot[k] = tot + (unsigned)d[k];
             R.msg[k] = msg + (unsigned)d[6 + k];
+            R.any_desc |= d[k] | d[6 + k];
         } else {
+            R.any_desc |= d[12] | d[13] | d[14] | d[15];
             R.psi[k] = A.psi + (size_t)f * A.psi_frame + (unsigned)d[12];
             R.dprev[k] = A.d1_prev + (size_t)f * A.d1_frame + (unsigned)d[13];
             R.dcur[k] = A.d1_cur ? A.d1_cur + (size_t)f * A.d1_frame + (unsigned)d[13] : nullptr;
@@ -385,8 +398,7 @@ __device__ __forceinline__ FixedRow<D, DS, Msg> fixed_row(const CodeDev &c, cons
 // iteration.
 template <int D, int DS, int K, int MODE, typename Msg>
 __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const CnArgs &A,
-                                            unsigned a, unsigned w, const PhiConsts &PK,
-                                            bool skip, bool &skipped) {
+                                            unsigned a, unsigned w, const PhiConsts &PK) {
     float lt[K][D];  // stored k: totals of iteration t-1; degree-1 k: Psi
     float mo[K][D];  // stored k: messages of iteration t-1
     uint64_t sw[K];  // syndrome words
@@ -406,13 +418,6 @@ __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const
                 if (base_mode(MODE) != kFirst) dw[q][k] = uniform_word(R.dprev[k] + wq);
             }
         }
-    }
-    // Every load above is issued before the frame-skip test, whose flag load
-    // then overlaps them (the empty asm keeps the loads on this side of it).
-    asm volatile("" ::: "memory");
-    if (skip) {
-        skipped = true;
-        return false;
     }
     float x[K][D];  // inputs L_vc of iteration t-1 (degree-1: Psi)
     bool dec[K][D]; // decisions of the voted iteration
@@ -505,7 +510,7 @@ __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const
 
 // How many of a thread's checks of a fixed row are processed at once (bounded
 // by registers for larger rows).
-template <int D> struct FixedChunk { static constexpr int value = D <= 3 ? 4 : (D <= 6 ? 2 : 1); };
+template <int D> struct FixedChunk { static constexpr int value = D <= 3 ? 4 : 1; };
 
 // The flag of the iteration a check-pass launch votes.
 template <int MODE>
@@ -523,30 +528,30 @@ __device__ __forceinline__ void vote_store(int32_t *flag, int32_t seen, bool bad
 
 // A common row at row_list position y, (degree, stored blocks) known at
 // compile time.  The frame-skip flag, the vote flag and the row descriptor
-// are independent scalar loads; the frame is skipped (its earlier check
-// succeeded) only after they are issued.
+// are independent scalar loads, issued together before the first wait.
 template <int D, int DS, int MODE, typename Msg, int CPT>
 __device__ __forceinline__ void check_row_fixed(const CodeDev &c, const CnArgs &A, int f, int y,
                                                 unsigned tile) {
-    const FixedRow<D, DS, Msg> R = fixed_row<D, DS, Msg>(c, A, f, y);
+    // The flag loads are unconditional (in bounds either way) scalar loads
+    // that issue together with the descriptor loads.
+    const PhiConsts PK = phi_consts();
     int32_t *flag = vote_flag<MODE>(A, f);
-    // both flag loads are unconditional (in bounds either way), so that they
-    // issue together with the descriptor loads
-    const int32_t seen = A.vote ? *flag : 1;
-    const int32_t prev = A.fail[(size_t)max(A.skip_after, 0) * A.F + f];
-    const bool skip = A.skip_after >= 0 && prev == 0;
+    const int32_t prev = uniform_i32(A.fail + (size_t)max(A.skip_after, 0) * A.F + f);
+    const int32_t seen = uniform_i32(flag);
+    const FixedRow<D, DS, Msg> R = fixed_row<D, DS, Msg>(c, A, f, y);
+    // The frame is skipped when its earlier check succeeded.  The test also
+    // reads the descriptor words (never negative), so their scalar loads issue
+    // together with the flag loads instead of after the branch.
+    const bool skip = (A.skip_after >= 0) & (prev == 0);
+    if (skip | (R.any_desc < 0)) return;
     constexpr int K = FixedChunk<D>::value < CPT ? FixedChunk<D>::value : CPT;
     const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned a0 = tile * (kBlock * CPT) + threadIdx.x;
     const unsigned w0 = tile * (4u * CPT) + wave;
-    const PhiConsts PK = phi_consts();
-    bool bad = false, skipped = false;
+    bool bad = false;
 #pragma unroll
-    for (int q0 = 0; q0 < CPT; q0 += K) {
-        bad |= fixed_chunk<D, DS, K, MODE, Msg>(R, A, a0 + q0 * kBlock, w0 + 4u * q0, PK, skip,
-                                                skipped);
-        if (skipped) return;
-    }
+    for (int q0 = 0; q0 < CPT; q0 += K)
+        bad |= fixed_chunk<D, DS, K, MODE, Msg>(R, A, a0 + q0 * kBlock, w0 + 4u * q0, PK);
     if (A.vote) vote_store(flag, seen, bad);
 }
 
