@@ -122,21 +122,16 @@ __global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A, uns
     variable_work<U, Msg>(c, A, f, (int)(i % (unsigned)c.NC), tile);
 }
 
-// Batch width of the variable pass: batches of about 20 loads (measured: wider
-// batches flood the memory pipeline, padded slots cost real loads), sized so
-// that they divide the column degree with little padding, e.g. 3 x 17 for 51.
 template <typename Msg>
 void launch_variable_pass(const CodeDev &c, const VnArgs &v, int F, hipStream_t st,
                           hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
-    const int u = variable_batch(c.max_core_deg);
-    const unsigned tl = (unsigned)((c.Z + kBlock - 1) / kBlock);
+    const unsigned tl = variable_tiles(c.Z);
     const dim3 g(xcd_grid(tl * (unsigned)c.NC * (unsigned)F));
-    switch (u) {
+    switch (variable_group(c.max_core_deg)) {
+        case 4: launch_timed(variable_pass<4, Msg>, g, st, start, stop, c, v, tl); break;
         case 8: launch_timed(variable_pass<8, Msg>, g, st, start, stop, c, v, tl); break;
-        case 11: launch_timed(variable_pass<11, Msg>, g, st, start, stop, c, v, tl); break;
+        case 13: launch_timed(variable_pass<13, Msg>, g, st, start, stop, c, v, tl); break;
         case 16: launch_timed(variable_pass<16, Msg>, g, st, start, stop, c, v, tl); break;
-        case 17: launch_timed(variable_pass<17, Msg>, g, st, start, stop, c, v, tl); break;
-        case 21: launch_timed(variable_pass<21, Msg>, g, st, start, stop, c, v, tl); break;
         default: launch_timed(variable_pass<26, Msg>, g, st, start, stop, c, v, tl); break;
     }
 }

@@ -44,14 +44,13 @@ struct SlotIndex {
     int begin[kEngineMaxSlots + 1];
 };
 
+// The slot of a work item: the largest s with begin[s] <= item.  Lane l tests
+// begin[l + 1] (one load per lane, one ballot), so the lookup costs one
+// memory round trip instead of a chain of dependent loads.
 __device__ __forceinline__ int find_slot(const SlotIndex &ix, int item) {
-    int lo = 0, hi = ix.n - 1;
-    while (lo < hi) {  // largest s with begin[s] <= item
-        const int mid = (lo + hi + 1) >> 1;
-        if (ix.begin[mid] <= item) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+    const int l = (int)(threadIdx.x & 63);
+    const int b = ix.begin[l + 1];
+    return __popcll(__ballot(l + 1 < ix.n && b <= item));
 }
 
 __device__ __forceinline__ bool checked_iter(const SlotDesc &S, int t) {
@@ -185,16 +184,15 @@ __global__ __launch_bounds__(kBlock) void engine_finalize(CodeDev c, FinArgs A) 
     finalize_work(c, A, blockIdx.y, blockIdx.x);
 }
 
-// The variable pass over all slots, batch width from the largest column degree.
+// The variable pass over all slots, group width from the largest column degree.
 template <typename Msg>
 void launch_engine_variable(dim3 g, dim3 b, hipStream_t st, const SlotDesc *slots, SlotIndex ix,
                             int step, int max_deg) {
-    switch (variable_batch(max_deg)) {
+    switch (variable_group(max_deg)) {
+        case 4: engine_variable_pass<Msg, 4><<<g, b, 0, st>>>(slots, ix, step); break;
         case 8: engine_variable_pass<Msg, 8><<<g, b, 0, st>>>(slots, ix, step); break;
-        case 11: engine_variable_pass<Msg, 11><<<g, b, 0, st>>>(slots, ix, step); break;
+        case 13: engine_variable_pass<Msg, 13><<<g, b, 0, st>>>(slots, ix, step); break;
         case 16: engine_variable_pass<Msg, 16><<<g, b, 0, st>>>(slots, ix, step); break;
-        case 17: engine_variable_pass<Msg, 17><<<g, b, 0, st>>>(slots, ix, step); break;
-        case 21: engine_variable_pass<Msg, 21><<<g, b, 0, st>>>(slots, ix, step); break;
         default: engine_variable_pass<Msg, 26><<<g, b, 0, st>>>(slots, ix, step); break;
     }
 }
@@ -352,7 +350,7 @@ bool Engine::admit_one(const Request &rq, int s) {
     D.slot_id = s;
     D.generation = sl.generation;
     D.cn_tiles = (int)check_tiles(rq.c.Z, cpt);
-    D.vn_tiles = (int)tiles_of(rq.c.Z);
+    D.vn_tiles = (int)variable_tiles(rq.c.Z);
 
     const CodeDev &c = rq.c;
     const int nfail = (rq.T + 1) * rq.F;

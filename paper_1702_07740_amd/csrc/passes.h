@@ -619,47 +619,70 @@ struct VnArgs {
     int F, t;
 };
 
-// Loads per batch of the variable pass for columns of degree <= max_deg: about
-// 20 per batch, rounded up to an instantiated width (8, 11, 16, 17, 21, 26).
-inline int variable_batch(int max_deg) {
-    const int nb = max_deg <= 0 ? 1 : (max_deg + 19) / 20;
-    const int u = (max_deg + nb - 1) / nb;
-    for (int w : {8, 11, 16, 17, 21, 26})
-        if (u <= w) return w;
+// Variable pass layout: the 4 waves of a workgroup split the blocks of one
+// core column into kVnGroups row groups, and each group's waves cover
+// kVnVars variables, so that every wave has one group's loads in flight at
+// once instead of running the whole column as a chain of dependent batches.
+constexpr int kVnGroups = 2;  // measured: 2 groups of 128 variables beat 1 x 256 and 4 x 64
+constexpr int kVnVars = kBlock / kVnGroups;
+inline unsigned variable_tiles(int Z) { return (unsigned)((Z + kVnVars - 1) / kVnVars); }
+
+// Loads per row group issued together: the group size ceil(max_deg / groups),
+// rounded up to an instantiated width (a longer group takes several batches).
+inline int variable_group(int max_deg) {
+    const int g = ((max_deg > 0 ? max_deg : 1) + kVnGroups - 1) / kVnGroups;
+    for (int w : {4, 8, 13, 16, 26})
+        if (g <= w) return w;
     return 26;
 }
 
-// Step 3 for the core columns: L_v = Q_v + sum of the column's messages, in
-// increasing row order (base 2: Q_v log2(e) plus the base-2 messages).  One thread per (core column k, position j).  The
-// messages are loaded U at a time with all U loads in flight together (a
-// column of degree <= U takes one batch); slots past the column's degree load
-// a clamped in-range entry and add 0.
-template <int U, typename Msg>
+// Step 3 for the core columns: L_v = Q_v + sum of the column's messages (in
+// base 2: Q_v log2(e) plus the base-2 messages).  Row group g (blocks
+// [g p, (g + 1) p), p = ceil(deg / groups)) is summed in increasing row order;
+// the group sums meet in LDS and L = (Q + S0) + S1 ..., a fixed order.
+// Messages of block (r, c) with shift s sit at (j - s) mod Z.
+template <int G, typename Msg>
 __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A, int f, int k,
                                               unsigned tile) {
+    constexpr int kWavesPerGroup = kBlock / 64 / kVnGroups;
+    __shared__ float part[kVnGroups][kVnVars];
     const unsigned Z = (unsigned)c.Z;
-    const unsigned j = tile * kBlock + threadIdx.x;
-    if (j >= Z) return;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int grp = w / kWavesPerGroup;
+    const unsigned v = (unsigned)(w % kWavesPerGroup) * 64 + (threadIdx.x & 63);  // variable in tile
+    const unsigned j = tile * kVnVars + v;
+    const unsigned jl = j < Z ? j : Z - 1;  // padding lanes load in range
     const Msg *msg = reinterpret_cast<const Msg *>(A.msg) + (size_t)f * A.msg_frame;
-    const float *llr = A.llr + (size_t)f * c.n + (size_t)c.core_col[k] * Z;
-    float L = at(llr, j) * kLog2e;
     const int deg = c.core_deg[k];
+    const int per = (deg + kVnGroups - 1) / kVnGroups;
+    const int b0 = grp * per, b1 = min(deg, b0 + per);
     const int32_t *tab = c.core_tab + (size_t)k * c.core_tab_stride;
-    for (int b = 0; b < deg; b += U) {
-        float v[U];
+    // group 0 also reads Q, issued with its message loads
+    const float *llr = A.llr + (size_t)f * c.n + (size_t)c.core_col[k] * Z;
+    const float q = (grp == 0) ? at(llr, jl) : 0.0f;
+    float p = 0.0f;
+    for (int b = b0; b < b1; b += G) {
+        float x[G];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = min(b + u, deg - 1);
+        for (int u = 0; u < G; ++u) {
+            const int i = min(b + u, b1 - 1);
             const unsigned s = (unsigned)tab[2 * i + 1];
-            const unsigned idx = (j >= s) ? j - s : j + Z - s;
-            v[u] = msg_load<Msg>(&at(msg + (unsigned)tab[2 * i], idx));
+            const unsigned idx = (jl >= s) ? jl - s : jl + Z - s;
+            x[u] = msg_load<Msg>(&at(msg + (unsigned)tab[2 * i], idx));
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) L += (b + u < deg) ? v[u] : 0.0f;
+        for (int u = 0; u < G; ++u) p += (b + u < b1) ? x[u] : 0.0f;
     }
-    float *row = A.tot + (size_t)f * A.tot_frame + (size_t)k * c.Zt;
-    at(row, j) = L;
-    at(row, j + Z) = L;
+    part[grp][v] = p;
+    __syncthreads();
+    if (grp == 0 && j < Z) {
+        float L = q * kLog2e;
+#pragma unroll
+        for (int g2 = 0; g2 < kVnGroups; ++g2) L += part[g2][v];
+        float *row = A.tot + (size_t)f * A.tot_frame + (size_t)k * c.Zt;
+        at(row, j) = L;
+        at(row, j + Z) = L;
+    }
 }
 
 // Pack the syndrome bytes into 64-bit words per base row: bit a%64 of word a/64.
