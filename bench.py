@@ -261,6 +261,57 @@ def workload_mixed(torch, ldpc, args):
     }
 
 
+def workload_small(torch, ldpc, args):
+    """The small template (Z = 64, n = 9,600), 16 frames at -15.4 dB, 100
+    iterations: launch-bound, so the decode is also replayed from a captured
+    HIP graph (the library allocates nothing and records no memsets)."""
+    from paper_1702_07740_amd import synth
+    Z, F, T = 64, 16, args.max_iters
+    base = synth.template_base(144, Z, seed=1)
+    code = ldpc.Code(base, Z)
+    x, Q = synth.biawgn_frames(code.n, F, args.snr, seed=2026)
+    dQ = torch.from_numpy(Q).cuda()
+    ds = code.syndrome(torch.from_numpy(x).cuda())
+    ws = code.alloc_workspace(F, T)
+    out = (torch.empty((F, code.n), dtype=torch.uint8, device="cuda"),
+           torch.empty(F, dtype=torch.int32, device="cuda"),
+           torch.empty(F, dtype=torch.uint8, device="cuda"), None)
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    eager_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws, out=out), args.steps)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        code.decode(dQ, ds, T, workspace=ws, out=out)
+        with torch.cuda.graph(graph, stream=side):
+            code.decode(dQ, ds, T, workspace=ws, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    graph_ms = timed(graph.replay, args.steps)
+    bits = F * code.n
+    return {
+        "metric": "raw decoded Mbit/s, small template n=9,600, 16 frames, 100 iters",
+        "value": round(bits / graph_ms / 1e3, 3), "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 3, "ms_per_step": graph_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"R=0.02 template, Z=64 (n=9,600), 16 BIAWGN frames at {args.snr} dB, "
+                               f"max {T} iterations, early stop; decode replayed from a HIP graph"},
+        "eager": {"ms_per_step": eager_ms, "mbit_s": round(bits / eager_ms / 1e3, 3)},
+        "avg_iters": float(out[1].float().mean().item()),
+    }
+
+
 def workload_frontend(torch, ldpc, args):
     """8-D reconciliation: Bob's message and Alice's LLRs on the device (octonion
     products), then FP16-message decoding of the n = 1,000,050 code; 8 frames."""
@@ -352,7 +403,7 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--workload", default="decode",
-                    choices=["decode", "mixed", "frontend", "serving"],
+                    choices=["decode", "mixed", "frontend", "serving", "small"],
                     help="decode: the n=1,000,050 headline; mixed: 64 frames of 9 codes in one "
                          "engine batch; frontend: 8-D reconciliation + FP16 decode; serving: "
                          "Poisson requests through the engine")
@@ -382,7 +433,7 @@ def main():
     from paper_1702_07740_amd import ldpc, synth
 
     if args.workload != "decode":
-        fn = {"mixed": workload_mixed, "frontend": workload_frontend,
+        fn = {"mixed": workload_mixed, "frontend": workload_frontend, "small": workload_small,
               "serving": workload_serving}[args.workload]
         print(json.dumps(fn(torch, ldpc, args)), flush=True)
         return

@@ -353,6 +353,46 @@ def test_timing_events(ldpc, oracle_mod):
     ev.close()
 
 
+def test_decode_replays_from_a_captured_graph(ldpc, oracle_mod):
+    """A whole decode (caller-owned workspace and outputs) captured by stream
+    capture replays bit-identically, several times, with eager work between
+    the replays (the graph holds kernels only: no memset or copy nodes)."""
+    Z, F, T = 64, 16, 40
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    x, Q = synth.biawgn_frames(g.n, F, -14.0, seed=31)
+    s = o.syndrome(x)
+    dQ, ds = _dev(Q), _dev(s)
+    ws = g.alloc_workspace(F, T)
+    out = (torch.empty((F, g.n), dtype=torch.uint8, device="cuda"),
+           torch.empty(F, dtype=torch.int32, device="cuda"),
+           torch.empty(F, dtype=torch.uint8, device="cuda"), None)
+    _say("graph capture", Z, F, T)
+    g.decode(dQ, ds, T, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    ref = [t.cpu().clone() for t in out[:3]]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        g.decode(dQ, ds, T, workspace=ws, out=out)
+        with torch.cuda.graph(graph, stream=side):
+            g.decode(dQ, ds, T, workspace=ws, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in out[:3]:
+            t.fill_(7)
+        junk = torch.randn(1 << 16, device="cuda").sum()  # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a, b in zip(ref, out[:3]):
+            assert torch.equal(a, b.cpu()), f"replay {rep}"
+    del graph
+
+
 # ------------------------------------------- full size (n = 1,000,050)
 @pytest.fixture(scope="module")
 def full_code(ldpc, oracle_mod):
