@@ -239,6 +239,7 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         }
         dd[16] = r * W;
         dd[17] = r;
+        dd[18] = cls_of(r);
     }
     const size_t o_rd = put(row_desc);
     // per core column: (message offset, shift) of its blocks at a fixed stride

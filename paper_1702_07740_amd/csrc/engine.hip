@@ -37,11 +37,23 @@ using namespace dev;
 
 constexpr int kStatusRing = 4;
 
-// What a launch needs to find its slot: work-item offsets by slot, in the
-// kernel arguments (no memory load before the lookup).
+// What a work item needs before its first dependent load, per active slot,
+// in the kernel arguments: with these a workgroup issues its row descriptor
+// (check pass) or column table (variable pass) and its flag loads together
+// with the loads of the slot's full descriptor, instead of after them.
+struct SlotHead {
+    const int32_t *tab;  // check pass: the code's row descriptors; variable pass: core_tab
+    int32_t *fail;
+    int32_t tiles;       // work tiles per row (check pass) or per core column (variable pass)
+    int32_t rows;        // mb (check pass) or NC (variable pass)
+    int32_t start_step, T, F, stride;  // stride: core_tab_stride (variable pass)
+};
+
+// Work-item offsets by slot and the slot heads, in the kernel arguments.
 struct SlotIndex {
     int n;
     int begin[kEngineMaxSlots + 1];
+    SlotHead head[kEngineMaxSlots];
 };
 
 // The slot of a work item: the largest s with begin[s] <= item.  Lane l tests
@@ -63,36 +75,37 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
     const int item = (int)xcd_item(blockIdx.x, (unsigned)ix.begin[ix.n]);
     if (item >= ix.begin[ix.n]) return;
     const int s = find_slot(ix, item);
-    const SlotDesc &S = slots[s];
-    const int t = step - S.start_step + 1;
-    if (t < 1 || t > S.T + 1) return;
+    const SlotHead &H = ix.head[s];
+    const int t = step - H.start_step + 1;
+    if (t < 1 || t > H.T + 1) return;
     int local = item - ix.begin[s];
-    const unsigned tile = (unsigned)(local % S.cn_tiles);
-    local /= S.cn_tiles;
-    const int y = local % S.c.mb;  // row_list position (every row of an engine code is common)
-    const int f = local / S.c.mb;
-    const bool vote_only = t == S.T + 1;
+    const unsigned tile = (unsigned)(local % H.tiles);
+    local /= H.tiles;
+    const int y = local % H.rows;  // row_list position (every row of an engine code is common)
+    const int f = local / H.rows;
+    const bool vote_only = t == H.T + 1;
+    const SlotDesc &S = slots[s];
     CnArgs A{};
     A.llr = S.llr;
     A.psi = S.psi;
     A.msg = S.msg;
     A.tot = S.tot;
     A.synbits = S.synbits;
-    A.fail = S.fail;
+    A.fail = H.fail;
     A.d1post = nullptr;
     A.msg_frame = S.L.msg_frame;
     A.tot_frame = S.L.tot_frame;
     A.d1_frame = S.L.d1bits_frame;
     A.syn_frame = S.L.synbits_frame;
     A.psi_frame = S.L.psi_frame;
-    A.F = S.F;
+    A.F = H.F;
     if (vote_only) {
-        A.t = S.T;
+        A.t = H.T;
         A.vote = 1;
-        A.d1_from_llr = S.T == 0;
-        A.d1_prev = S.d1b[S.T & 1];
+        A.d1_from_llr = H.T == 0;
+        A.d1_prev = S.d1b[H.T & 1];
         A.d1_cur = nullptr;
-        A.skip_after = S.T >= 1 ? S.T - 1 : -1;
+        A.skip_after = H.T >= 1 ? H.T - 1 : -1;
     } else {
         A.t = t;
         A.vote = checked_iter(S, t - 1) ? 1 : 0;
@@ -101,12 +114,15 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
         A.d1_cur = S.d1b[t & 1];
         A.skip_after = t >= 2 ? t - 2 : -1;
     }
+    // the row descriptor through the slot head (its address needs no slot load)
+    CodeDev c = S.c;
+    c.row_desc = H.tab;
     if (vote_only)
-        check_work<Msg, false, kVoteOnly, CPT>(S.c, A, f, y, tile);
+        check_work_by_desc<Msg, kVoteOnly, CPT>(c, A, f, y, tile);
     else if (t == 1)
-        check_work<Msg, false, kFirst, CPT>(S.c, A, f, y, tile);
+        check_work_by_desc<Msg, kFirst, CPT>(c, A, f, y, tile);
     else
-        check_work<Msg, false, kSteady, CPT>(S.c, A, f, y, tile);
+        check_work_by_desc<Msg, kSteady, CPT>(c, A, f, y, tile);
 }
 
 template <typename Msg, int U>
@@ -115,25 +131,30 @@ __global__ __launch_bounds__(kBlock) void engine_variable_pass(const SlotDesc *s
     const int item = (int)xcd_item(blockIdx.x, (unsigned)ix.begin[ix.n]);
     if (item >= ix.begin[ix.n]) return;
     const int s = find_slot(ix, item);
-    const SlotDesc &S = slots[s];
-    const int t = step - S.start_step + 1;
-    if (t < 1 || t > S.T) return;
+    const SlotHead &H = ix.head[s];
+    const int t = step - H.start_step + 1;
+    if (t < 1 || t > H.T) return;
     int local = item - ix.begin[s];
-    const unsigned tile = (unsigned)(local % S.vn_tiles);
-    local /= S.vn_tiles;
-    const int k = local % S.c.NC;
-    const int f = local / S.c.NC;
-    if (S.fail[(size_t)(t - 1) * S.F + f] == 0) return;
+    const unsigned tile = (unsigned)(local % H.tiles);
+    local /= H.tiles;
+    const int k = local % H.rows;
+    const int f = local / H.rows;
+    if (uniform_i32(H.fail + (size_t)(t - 1) * H.F + f) == 0) return;
+    const SlotDesc &S = slots[s];
     VnArgs V{};
     V.llr = S.llr;
     V.msg = S.msg;
     V.tot = S.tot;
-    V.fail = S.fail;
+    V.fail = H.fail;
     V.msg_frame = S.L.msg_frame;
     V.tot_frame = S.L.tot_frame;
-    V.F = S.F;
+    V.F = H.F;
     V.t = t;
-    variable_work<U, Msg>(S.c, V, f, k, tile);
+    // the column table through the slot head (its address needs no slot load)
+    CodeDev c = S.c;
+    c.core_tab = H.tab;
+    c.core_tab_stride = H.stride;
+    variable_work<U, Msg>(c, V, f, k, tile);
 }
 
 // Per active slot: frames whose parity check has not succeeded by the last
@@ -465,6 +486,9 @@ hipError_t Engine::step(int *active_out, int *queued_out) {
             const SlotDesc &D = slot[order[i]].desc;
             cn.begin[i] = cn_total;
             vn.begin[i] = vn_total;
+            cn.head[i] = SlotHead{D.c.row_desc, D.fail, D.cn_tiles, D.c.mb, D.start_step, D.T, D.F, 0};
+            vn.head[i] = SlotHead{D.c.core_tab, D.fail, D.vn_tiles, D.c.NC, D.start_step, D.T, D.F,
+                                  D.c.core_tab_stride};
             cn_total += D.cn_tiles * D.c.mb * D.F;
             vn_total += D.vn_tiles * D.c.NC * D.F;
         }

@@ -74,6 +74,7 @@ struct CodeDev {
     //   12..15  degree-1 block: Psi offset (index * Zp), decision-word offset
     //           (index * W), channel-LLR offset (column * Z), shift
     //   16, 17  syndrome-word offset (r * W), base row r
+    //   18      the row's class
     const int32_t *row_desc;
     // per block: shift, kind, ref (state index or degree-1 index), column,
     // core index of the column (state blocks only, else -1)

@@ -610,6 +610,24 @@ __device__ __forceinline__ void check_work(const CodeDev &c, const CnArgs &A, in
 #undef LDPC_CLASS
 }
 
+// Common-row check update of one work item whose class is read from word 18
+// of the row's descriptor (used where the class boundaries would cost a load
+// before the descriptor's: the multi-request engine).
+template <typename Msg, int MODE, int CPT>
+__device__ __forceinline__ void check_work_by_desc(const CodeDev &c, const CnArgs &A, int f, int y,
+                                                   unsigned tile) {
+#define LDPC_CLASS(I, D, S) \
+    case I: check_row_fixed<D, S, MODE, Msg, CPT>(c, A, f, y, tile); break;
+    static_assert(kFixedClasses == 12, "class list below covers degrees 1..6");
+    switch (uniform_i32(c.row_desc + (size_t)y * kRowDescWords + 18)) {
+        LDPC_CLASS(0, 1, 0) LDPC_CLASS(1, 1, 1) LDPC_CLASS(2, 2, 1) LDPC_CLASS(3, 2, 2)
+        LDPC_CLASS(4, 3, 2) LDPC_CLASS(5, 3, 3) LDPC_CLASS(6, 4, 3) LDPC_CLASS(7, 4, 4)
+        LDPC_CLASS(8, 5, 4) LDPC_CLASS(9, 5, 5) LDPC_CLASS(10, 6, 5) LDPC_CLASS(11, 6, 6)
+        default: break;
+    }
+#undef LDPC_CLASS
+}
+
 struct VnArgs {
     const float *llr;
     const void *msg;
