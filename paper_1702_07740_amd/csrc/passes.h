@@ -44,7 +44,7 @@ constexpr float kPhiHi = 4.328084946e+01f;
 //                     H a degree-3 near-minimax fit of the smooth remainder
 //                     (the expansion of -ln(tanh(y)/y) about 0, rescaled);
 //   b >= 1.5 log2(e): phi2(b) = log2(e) 2 atanh(t), t = 2^-b = e^-x, by its
-//                     odd series to t^7 (t <= 0.223; truncation below 4e-7).
+//                     odd series to t^7 (t <= 0.223; truncation below 7e-7).
 // Each branch takes one hardware transcendental (log2 or exp2).  Relative
 // error in FP32 below 1e-6 over the whole clamped range.
 struct PhiConsts {
