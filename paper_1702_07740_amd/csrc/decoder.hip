@@ -119,13 +119,13 @@ __global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A, uns
     i /= tiles;
     const int f = (int)(i / (unsigned)c.NC);
     if (A.fail[(size_t)(A.t - 1) * A.F + f] == 0) return;
-    variable_work<U, Msg>(c, A, f, (int)(i % (unsigned)c.NC), tile);
+    variable_work<U, Msg, vn_vpt<Msg>()>(c, A, f, (int)(i % (unsigned)c.NC), tile);
 }
 
 template <typename Msg>
 void launch_variable_pass(const CodeDev &c, const VnArgs &v, int F, hipStream_t st,
                           hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
-    const unsigned tl = variable_tiles(c.Z);
+    const unsigned tl = variable_tiles(c.Z, vn_vpt<Msg>());
     const dim3 g(xcd_grid(tl * (unsigned)c.NC * (unsigned)F));
     switch (variable_group(c.max_core_deg)) {
         case 4: launch_timed(variable_pass<4, Msg>, g, st, start, stop, c, v, tl); break;

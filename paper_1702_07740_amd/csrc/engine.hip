@@ -125,6 +125,8 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
         check_work_by_desc<Msg, kSteady, CPT>(c, A, f, y, tile);
 }
 
+// The variable pass over all slots (one variable per thread), with the batch
+// width of the largest column degree among them.
 template <typename Msg, int U>
 __global__ __launch_bounds__(kBlock) void engine_variable_pass(const SlotDesc *slots, SlotIndex ix,
                                                                int step) {
@@ -154,7 +156,19 @@ __global__ __launch_bounds__(kBlock) void engine_variable_pass(const SlotDesc *s
     CodeDev c = S.c;
     c.core_tab = H.tab;
     c.core_tab_stride = H.stride;
-    variable_work<U, Msg>(c, V, f, k, tile);
+    variable_work<U, Msg, 1>(c, V, f, k, tile);
+}
+
+template <typename Msg>
+void launch_engine_variable(dim3 g, dim3 b, hipStream_t st, const SlotDesc *slots, SlotIndex ix,
+                            int step, int max_deg) {
+    switch (variable_group(max_deg)) {
+        case 4: engine_variable_pass<Msg, 4><<<g, b, 0, st>>>(slots, ix, step); break;
+        case 8: engine_variable_pass<Msg, 8><<<g, b, 0, st>>>(slots, ix, step); break;
+        case 13: engine_variable_pass<Msg, 13><<<g, b, 0, st>>>(slots, ix, step); break;
+        case 16: engine_variable_pass<Msg, 16><<<g, b, 0, st>>>(slots, ix, step); break;
+        default: engine_variable_pass<Msg, 26><<<g, b, 0, st>>>(slots, ix, step); break;
+    }
 }
 
 // Per active slot: frames whose parity check has not succeeded by the last
@@ -203,19 +217,6 @@ __global__ __launch_bounds__(64) void engine_frame_exit(FinArgs A) { frame_exit_
 
 __global__ __launch_bounds__(kBlock) void engine_finalize(CodeDev c, FinArgs A) {
     finalize_work(c, A, blockIdx.y, blockIdx.x);
-}
-
-// The variable pass over all slots, group width from the largest column degree.
-template <typename Msg>
-void launch_engine_variable(dim3 g, dim3 b, hipStream_t st, const SlotDesc *slots, SlotIndex ix,
-                            int step, int max_deg) {
-    switch (variable_group(max_deg)) {
-        case 4: engine_variable_pass<Msg, 4><<<g, b, 0, st>>>(slots, ix, step); break;
-        case 8: engine_variable_pass<Msg, 8><<<g, b, 0, st>>>(slots, ix, step); break;
-        case 13: engine_variable_pass<Msg, 13><<<g, b, 0, st>>>(slots, ix, step); break;
-        case 16: engine_variable_pass<Msg, 16><<<g, b, 0, st>>>(slots, ix, step); break;
-        default: engine_variable_pass<Msg, 26><<<g, b, 0, st>>>(slots, ix, step); break;
-    }
 }
 
 inline unsigned tiles_of(int n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -371,7 +372,7 @@ bool Engine::admit_one(const Request &rq, int s) {
     D.slot_id = s;
     D.generation = sl.generation;
     D.cn_tiles = (int)check_tiles(rq.c.Z, cpt);
-    D.vn_tiles = (int)variable_tiles(rq.c.Z);
+    D.vn_tiles = (int)variable_tiles(rq.c.Z, 1);
 
     const CodeDev &c = rq.c;
     const int nfail = (rq.T + 1) * rq.F;

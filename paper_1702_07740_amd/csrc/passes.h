@@ -639,14 +639,23 @@ struct VnArgs {
 
 // Variable pass layout: the 4 waves of a workgroup split the blocks of one
 // core column into kVnGroups row groups, and each group's waves cover
-// kVnVars variables, so that every wave has one group's loads in flight at
-// once instead of running the whole column as a chain of dependent batches.
+// kVnLanes variables (kVnLanes * VPT with VPT variables per thread), so that
+// every wave has one group's loads in flight at once instead of running the
+// whole column as a chain of dependent batches.
 constexpr int kVnGroups = 2;  // measured: 2 groups of 128 variables beat 1 x 256 and 4 x 64
-constexpr int kVnVars = kBlock / kVnGroups;
-inline unsigned variable_tiles(int Z) { return (unsigned)((Z + kVnVars - 1) / kVnVars); }
+constexpr int kVnLanes = kBlock / kVnGroups;
+// Variables per thread (VPT): the single-call decoder takes 2 for
+// half-precision messages, whose loads are latency-bound at one variable per
+// thread, else 1.
+template <typename Msg> constexpr int vn_vpt() { return sizeof(Msg) == 2 ? 2 : 1; }
+inline unsigned variable_tiles(int Z, int vpt) {
+    const int v = kVnLanes * vpt;
+    return (unsigned)((Z + v - 1) / v);
+}
 
-// Loads per row group issued together: the group size ceil(max_deg / groups),
-// rounded up to an instantiated width (a longer group takes several batches).
+// Loads per row group and variable issued together: the group size
+// ceil(max_deg / groups), rounded up to an instantiated width (a longer group
+// takes several batches).
 inline int variable_group(int max_deg) {
     const int g = ((max_deg > 0 ? max_deg : 1) + kVnGroups - 1) / kVnGroups;
     for (int w : {4, 8, 13, 16, 26})
@@ -659,17 +668,22 @@ inline int variable_group(int max_deg) {
 // [g p, (g + 1) p), p = ceil(deg / groups)) is summed in increasing row order;
 // the group sums meet in LDS and L = (Q + S0) + S1 ..., a fixed order.
 // Messages of block (r, c) with shift s sit at (j - s) mod Z.
-template <int G, typename Msg>
+template <int G, typename Msg, int VPT>
 __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A, int f, int k,
                                               unsigned tile) {
     constexpr int kWavesPerGroup = kBlock / 64 / kVnGroups;
-    __shared__ float part[kVnGroups][kVnVars];
+    constexpr int V = kVnLanes * VPT;  // variables per workgroup
+    __shared__ float part[kVnGroups][V];
     const unsigned Z = (unsigned)c.Z;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int grp = w / kWavesPerGroup;
-    const unsigned v = (unsigned)(w % kWavesPerGroup) * 64 + (threadIdx.x & 63);  // variable in tile
-    const unsigned j = tile * kVnVars + v;
-    const unsigned jl = j < Z ? j : Z - 1;  // padding lanes load in range
+    const unsigned v0 = (unsigned)(w % kWavesPerGroup) * 64 + (threadIdx.x & 63);
+    unsigned j[VPT], jl[VPT];
+#pragma unroll
+    for (int e = 0; e < VPT; ++e) {
+        j[e] = tile * V + v0 + e * kVnLanes;
+        jl[e] = j[e] < Z ? j[e] : Z - 1;  // padding lanes load in range
+    }
     const Msg *msg = reinterpret_cast<const Msg *>(A.msg) + (size_t)f * A.msg_frame;
     const int deg = c.core_deg[k];
     const int per = (deg + kVnGroups - 1) / kVnGroups;
@@ -677,29 +691,44 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
     const int32_t *tab = c.core_tab + (size_t)k * c.core_tab_stride;
     // group 0 also reads Q, issued with its message loads
     const float *llr = A.llr + (size_t)f * c.n + (size_t)c.core_col[k] * Z;
-    const float q = (grp == 0) ? at(llr, jl) : 0.0f;
-    float p = 0.0f;
+    float q[VPT], p[VPT];
+#pragma unroll
+    for (int e = 0; e < VPT; ++e) {
+        q[e] = (grp == 0) ? at(llr, jl[e]) : 0.0f;
+        p[e] = 0.0f;
+    }
     for (int b = b0; b < b1; b += G) {
-        float x[G];
+        float x[VPT][G];
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int i = min(b + u, b1 - 1);
             const unsigned s = (unsigned)tab[2 * i + 1];
-            const unsigned idx = (jl >= s) ? jl - s : jl + Z - s;
-            x[u] = msg_load<Msg>(&at(msg + (unsigned)tab[2 * i], idx));
+            const Msg *blk = msg + (unsigned)tab[2 * i];
+#pragma unroll
+            for (int e = 0; e < VPT; ++e) {
+                const unsigned idx = (jl[e] >= s) ? jl[e] - s : jl[e] + Z - s;
+                x[e][u] = msg_load<Msg>(&at(blk, idx));
+            }
         }
 #pragma unroll
-        for (int u = 0; u < G; ++u) p += (b + u < b1) ? x[u] : 0.0f;
-    }
-    part[grp][v] = p;
-    __syncthreads();
-    if (grp == 0 && j < Z) {
-        float L = q * kLog2e;
+        for (int e = 0; e < VPT; ++e)
 #pragma unroll
-        for (int g2 = 0; g2 < kVnGroups; ++g2) L += part[g2][v];
+            for (int u = 0; u < G; ++u) p[e] += (b + u < b1) ? x[e][u] : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < VPT; ++e) part[grp][v0 + e * kVnLanes] = p[e];
+    __syncthreads();
+    if (grp == 0) {
         float *row = A.tot + (size_t)f * A.tot_frame + (size_t)k * c.Zt;
-        at(row, j) = L;
-        at(row, j + Z) = L;
+#pragma unroll
+        for (int e = 0; e < VPT; ++e) {
+            if (j[e] >= Z) continue;
+            float L = q[e] * kLog2e;
+#pragma unroll
+            for (int g2 = 0; g2 < kVnGroups; ++g2) L += part[g2][v0 + e * kVnLanes];
+            at(row, j[e]) = L;
+            at(row, j[e] + Z) = L;
+        }
     }
 }
 
