@@ -263,8 +263,11 @@ def workload_mixed(torch, ldpc, args):
 
 def workload_small(torch, ldpc, args):
     """The small template (Z = 64, n = 9,600), 16 frames at -15.4 dB, 100
-    iterations: launch-bound, so the decode is also replayed from a captured
-    HIP graph (the library allocates nothing and records no memsets)."""
+    iterations.  Launch-bound on the per-iteration schedule, so the default
+    schedule here is the frame-resident one (one launch per decode, state in
+    LDS).  Also timed: the per-iteration launches, eager and replayed from a
+    captured HIP graph, FP16 messages, and the resident schedule at more
+    frames."""
     from paper_1702_07740_amd import synth
     Z, F, T = 64, 16, args.max_iters
     base = synth.template_base(144, Z, seed=1)
@@ -289,26 +292,52 @@ def workload_small(torch, ldpc, args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    eager_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws, out=out), args.steps)
+    bits = F * code.n
+    auto = code.schedule(F=F)
+    auto_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws, out=out), args.steps)
+    avg_iters = float(out[1].float().mean().item())
+    res_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws, out=out, schedule="resident"),
+                   args.steps)
+    ws16 = code.alloc_workspace(F, T, msg_fp16=True)
+    res16_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws16, out=out, msg_fp16=True,
+                                         schedule="resident"), args.steps)
+    eager_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws, out=out, schedule="launches"),
+                     args.steps)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.stream(side):
-        code.decode(dQ, ds, T, workspace=ws, out=out)
+        code.decode(dQ, ds, T, workspace=ws, out=out, schedule="launches")
         with torch.cuda.graph(graph, stream=side):
-            code.decode(dQ, ds, T, workspace=ws, out=out)
+            code.decode(dQ, ds, T, workspace=ws, out=out, schedule="launches")
     torch.cuda.current_stream().wait_stream(side)
     graph_ms = timed(graph.replay, args.steps)
-    bits = F * code.n
+    del graph
+    sweep = {}
+    for Fs in (64, 256, 1024):
+        xs, Qs = synth.biawgn_frames(code.n, Fs, args.snr, seed=2027)
+        dQs = torch.from_numpy(Qs).cuda()
+        dss = code.syndrome(torch.from_numpy(xs).cuda())
+        wss = code.alloc_workspace(Fs, T)
+        for sch in ("resident", "launches"):
+            ms = timed(lambda: code.decode(dQs, dss, T, workspace=wss, schedule=sch),
+                       max(3, args.steps // 4))
+            sweep.setdefault(str(Fs), {})[sch] = {"ms": ms, "mbit_s": round(Fs * code.n / ms / 1e3, 3)}
+        sweep[str(Fs)]["auto"] = code.schedule(F=Fs)
+        del dQs, dss, wss
     return {
         "metric": "raw decoded Mbit/s, small template n=9,600, 16 frames, 100 iters",
-        "value": round(bits / graph_ms / 1e3, 3), "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": 3, "ms_per_step": graph_ms, "higher_is_better": True, "scaling": "weak",
+        "value": round(bits / auto_ms / 1e3, 3), "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 3, "ms_per_step": auto_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"R=0.02 template, Z=64 (n=9,600), 16 BIAWGN frames at {args.snr} dB, "
-                               f"max {T} iterations, early stop; decode replayed from a HIP graph"},
-        "eager": {"ms_per_step": eager_ms, "mbit_s": round(bits / eager_ms / 1e3, 3)},
-        "avg_iters": float(out[1].float().mean().item()),
+                               f"max {T} iterations, early stop; automatic schedule ({auto})"},
+        "resident": {"ms_per_step": res_ms, "mbit_s": round(bits / res_ms / 1e3, 3)},
+        "resident_fp16": {"ms_per_step": res16_ms, "mbit_s": round(bits / res16_ms / 1e3, 3)},
+        "launches_eager": {"ms_per_step": eager_ms, "mbit_s": round(bits / eager_ms / 1e3, 3)},
+        "launches_graph": {"ms_per_step": graph_ms, "mbit_s": round(bits / graph_ms / 1e3, 3)},
+        "resident_frames": sweep,
+        "avg_iters": avg_iters,
     }
 
 

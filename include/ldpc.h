@@ -111,11 +111,39 @@ typedef struct {
                                 check pass of iteration t, 4(t-1)+2, 4(t-1)+3 at
                                 the start and end of its variable pass            */
     int32_t n_timing_events; /* >= 4*max_iters when timing_events is set          */
+    int32_t schedule;        /* LDPC_SCHEDULE_*: how the iterations are launched;
+                                results are identical on every schedule           */
 } ldpc_decode_opts;
 
+/*
+ * Decode schedules.  Both run the flooding schedule of Alg. 1 with the same
+ * arithmetic in the same order, so outputs are bit-identical.
+ *  LAUNCHES  two launches per iteration (check pass, variable pass) over all
+ *            frames, state in HBM: any code, posteriors and timing events.
+ *  RESIDENT  one launch for the whole decode, one 1024-thread workgroup per
+ *            frame holding the frame's messages, core totals and bit arrays in
+ *            LDS: for small liftings, where the per-iteration launches are
+ *            latency-bound.  Needs llr_out and timing_events unset and the
+ *            frame's state within one workgroup's LDS (160 KB on MI355X:
+ *            state edges * (4 or 2 bytes) + core variables * 4 + bit arrays).
+ *  AUTO      RESIDENT when it is possible and a cost model of both, fitted
+ *            to measurements, favours it (many frames of a small code), else
+ *            LAUNCHES.
+ */
+enum { LDPC_SCHEDULE_AUTO = 0, LDPC_SCHEDULE_LAUNCHES = 1, LDPC_SCHEDULE_RESIDENT = 2 };
+
 /* Fill opts with the defaults {early_stop=1, check_from_iter=0, msg_fp16=0,
- * checks_per_thread=0, llr_out=NULL, timing_events=NULL, n_timing_events=0}. */
+ * checks_per_thread=0, llr_out=NULL, timing_events=NULL, n_timing_events=0,
+ * schedule=LDPC_SCHEDULE_AUTO}. */
 void ldpc_decode_opts_init(ldpc_decode_opts *opts);
+
+/* The schedule (LDPC_SCHEDULE_LAUNCHES or LDPC_SCHEDULE_RESIDENT) that
+ * ldpc_decode_batch runs for F frames with these options (NULL = defaults).
+ *   schedule_out  host
+ * Errors: LDPC_EINVAL (null, F outside [1, 65535], schedule out of range),
+ * LDPC_EUNSUPPORTED (RESIDENT requested where it is not possible). */
+int ldpc_decode_schedule(const ldpc_code *code, int32_t F, const ldpc_decode_opts *opts,
+                         int32_t *schedule_out);
 
 /* Workspace bytes ldpc_decode_batch needs for F frames and max_iters iterations
  * with these options (NULL = defaults).  Returns 0 on an invalid argument. */
@@ -140,8 +168,10 @@ size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
  * independent: frame f's outputs depend only on frame f's inputs, bit for bit,
  * whatever F and the other frames are.
  * Errors: LDPC_EINVAL (F < 1, max_iters < 0, check_from_iter < 0, null
- * pointer, checks_per_thread not 0/1/2/4, too few timing events), LDPC_EWORKSPACE, LDPC_EDEVICE (current device is
- * not the code's device, or a launch failed).
+ * pointer, checks_per_thread not 0/1/2/4, schedule out of range, too few
+ * timing events), LDPC_EUNSUPPORTED (RESIDENT requested where it is not
+ * possible), LDPC_EWORKSPACE, LDPC_EDEVICE (current device is not the code's
+ * device, or a launch failed).
  */
 int ldpc_decode_batch(const ldpc_code *code, int32_t F,
                       const float *llr, const uint8_t *syndrome, int32_t max_iters,

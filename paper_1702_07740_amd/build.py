@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libldpc.so")
-SOURCES = ["api.hip", "decoder.hip", "engine.hip", "frontend.hip"]
+SOURCES = ["api.hip", "decoder.hip", "engine.hip", "frontend.hip", "resident.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

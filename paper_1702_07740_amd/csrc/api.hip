@@ -17,6 +17,7 @@ using ldpc::CodeDev;
 struct ldpc_code {
     ldpc_code_info_t info;
     int device;
+    size_t lds_limit;       // LDS bytes one workgroup may take on that device
     CodeDev dev;            // sizes + device table pointers
     int32_t *table;         // one device allocation holding every table
 };
@@ -73,6 +74,7 @@ void ldpc_decode_opts_init(ldpc_decode_opts *o) {
     o->llr_out = nullptr;
     o->timing_events = nullptr;
     o->n_timing_events = 0;
+    o->schedule = LDPC_SCHEDULE_AUTO;
 }
 
 int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldpc_code **out) {
@@ -261,6 +263,13 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         delete code;
         return fail_with(LDPC_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
     }
+    int lds = 0;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, code->device);
+    if (e != hipSuccess) {
+        delete code;
+        return fail_with(LDPC_EDEVICE, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
+    }
+    code->lds_limit = lds > 0 ? (size_t)lds : 0;
     e = hipMalloc(reinterpret_cast<void **>(&code->table), host.size() * sizeof(int32_t));
     if (e != hipSuccess) {
         delete code;
@@ -351,6 +360,78 @@ size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
     return ldpc::work_layout(code->dev, F, max_iters, o.msg_fp16 != 0, o.llr_out != nullptr).total;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The schedule a decode of F frames with options o runs on: the resident one
+// needs no posterior output and no per-pass events, and the frame's state
+// must fit in one workgroup's LDS.  Automatic choice by a cost model per
+// iteration, fitted to measurements on MI355X: the resident schedule takes
+// about kResidentUnitNs per (base row, 64 checks) unit of a frame, for every
+// round of up to kResidentFramesPerRound frames (one workgroup per CU); the
+// launches take kLaunchFixedNs plus kLaunchWgNs per workgroup of the two
+// passes (256-thread check tiles of 256 * cpt checks, variable tiles of 128
+// or, with half messages, 256 variables).
+constexpr double kResidentUnitNs = 115.0;
+constexpr int kResidentFramesPerRound = 256;
+constexpr double kLaunchFixedNs = 7000.0;
+constexpr double kLaunchWgNs = 2.35;
+
+bool resident_pays(const CodeDev &c, int F, int cpt, bool fp16) {
+    const double units = (double)c.mb * c.W;
+    const double rounds = (double)((F + kResidentFramesPerRound - 1) / kResidentFramesPerRound);
+    const double t_res = rounds * units * kResidentUnitNs;
+    const int vn = fp16 ? 256 : 128;
+    const double wgs = (double)F * ((double)c.mb * ((c.Z + 256 * cpt - 1) / (256 * cpt)) +
+                                    (double)c.NC * ((c.Z + vn - 1) / vn));
+    return t_res < kLaunchFixedNs + kLaunchWgNs * wgs;
+}
+
+int resolve_schedule(const ldpc_code *code, int F, const ldpc_decode_opts &o, int *out) {
+    if (o.checks_per_thread != 0 && o.checks_per_thread != 1 && o.checks_per_thread != 2 &&
+        o.checks_per_thread != 4)
+        return fail_with(LDPC_EINVAL, "checks_per_thread = %d is not 0, 1, 2 or 4",
+                         o.checks_per_thread);
+    if (o.schedule < LDPC_SCHEDULE_AUTO || o.schedule > LDPC_SCHEDULE_RESIDENT)
+        return fail_with(LDPC_EINVAL, "schedule = %d is not 0, 1 or 2", o.schedule);
+    const bool possible = !o.llr_out && !o.timing_events &&
+                          ldpc::resident_layout(code->dev, o.msg_fp16 != 0).total <= code->lds_limit;
+    if (o.schedule == LDPC_SCHEDULE_RESIDENT && !possible)
+        return fail_with(LDPC_EUNSUPPORTED,
+                         "resident schedule: needs llr_out and timing_events unset and %zu LDS "
+                         "bytes (limit %zu)",
+                         ldpc::resident_layout(code->dev, o.msg_fp16 != 0).total, code->lds_limit);
+    if (o.schedule == LDPC_SCHEDULE_AUTO)
+        *out = (possible && resident_pays(code->dev, F, o.checks_per_thread == 0
+                                                            ? ldpc::kDefaultChecksPerThread
+                                                            : o.checks_per_thread,
+                                          o.msg_fp16 != 0))
+                   ? LDPC_SCHEDULE_RESIDENT
+                   : LDPC_SCHEDULE_LAUNCHES;
+    else
+        *out = o.schedule;
+    return LDPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldpc_decode_schedule(const ldpc_code *code, int32_t F, const ldpc_decode_opts *opts,
+                         int32_t *schedule_out) {
+    if (!code || !schedule_out) return fail_with(LDPC_EINVAL, "null pointer");
+    if (F < 1 || F > 65535) return fail_with(LDPC_EINVAL, "F = %d outside [1, 65535]", F);
+    ldpc_decode_opts o;
+    ldpc_decode_opts_init(&o);
+    if (opts) o = *opts;
+    int sched = 0;
+    const int st = resolve_schedule(code, F, o, &sched);
+    if (st != LDPC_OK) return st;
+    *schedule_out = sched;
+    return LDPC_OK;
+}
+
 int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const uint8_t *syndrome,
                       int32_t max_iters, uint8_t *bits_out, int32_t *iters_out,
                       uint8_t *converged_out, const ldpc_decode_opts *opts, void *workspace,
@@ -378,7 +459,10 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const 
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return fail_with(LDPC_EWORKSPACE, "workspace %p of %zu bytes; need %zu bytes, 256-aligned",
                          workspace, workspace_bytes, need);
-    int st = check_device(code);
+    int sched = 0;
+    int st = resolve_schedule(code, F, o, &sched);
+    if (st != LDPC_OK) return st;
+    st = check_device(code);
     if (st != LDPC_OK) return st;
 
     ldpc::DecodeLaunch l{};
@@ -398,7 +482,11 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const 
     l.ws = static_cast<char *>(workspace);
     l.events = reinterpret_cast<hipEvent_t *>(o.timing_events);
     l.stream = static_cast<hipStream_t>(stream);
-    hipError_t e = ldpc::enqueue_decode(l);
+    hipError_t e = sched == LDPC_SCHEDULE_RESIDENT
+                       ? ldpc::enqueue_resident(l, ldpc::work_layout(l.c, F, max_iters, l.fp16 != 0,
+                                                                     false),
+                                                code->lds_limit)
+                       : ldpc::enqueue_decode(l);
     if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
     return LDPC_OK;
 }

@@ -126,6 +126,29 @@ struct DecodeLaunch {
 // Enqueue the whole decode on l.stream.  Returns hipSuccess or the first
 // launch error.
 hipError_t enqueue_decode(const DecodeLaunch &l);
+
+// Frame-resident schedule (resident.hip): one workgroup per frame runs every
+// iteration with the frame's state in LDS.  Byte offsets of that state:
+struct ResidentLayout {
+    size_t tot, syn, d1, flag, total;  // messages at 0; total = LDS bytes per workgroup
+};
+ResidentLayout resident_layout(const CodeDev &c, bool fp16);
+
+struct ResidentArgs {
+    const float *llr;          // [F][n]
+    const uint8_t *syndrome;   // [F][m]
+    float *psi;                // [F][ND1][Zp] degree-1 inputs (decode workspace)
+    uint8_t *bits_out;
+    int32_t *iters_out;
+    uint8_t *conv_out;
+    size_t psi_frame;
+    int T, early_stop, check_from;
+    unsigned lds_tot, lds_syn, lds_d1, lds_flag;
+};
+
+// Enqueue a whole decode as one resident launch (no posteriors, no per-pass
+// events).  hipErrorInvalidValue if the state exceeds lds_limit bytes.
+hipError_t enqueue_resident(const DecodeLaunch &l, const WorkLayout &W, size_t lds_limit);
 hipError_t enqueue_syndrome(const CodeDev &c, int F, const uint8_t *bits, uint8_t *syn,
                             hipStream_t stream);
 hipError_t enqueue_reconciliation_llr(int d, int F, int n, const float *x, const float *m,

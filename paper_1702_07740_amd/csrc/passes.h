@@ -663,6 +663,17 @@ inline int variable_group(int max_deg) {
     return 26;
 }
 
+// L = (Q log2(e) + S0) + S1 ...: the product rounded on its own (never fused
+// into the first addition), so every schedule that sums the same groups
+// gets the same bits.
+__device__ __forceinline__ float core_total(float q, const float (&part)[kVnGroups]) {
+#pragma clang fp contract(off)
+    float L = q * kLog2e;
+#pragma unroll
+    for (int g = 0; g < kVnGroups; ++g) L += part[g];
+    return L;
+}
+
 // Step 3 for the core columns: L_v = Q_v + sum of the column's messages (in
 // base 2: Q_v log2(e) plus the base-2 messages).  Row group g (blocks
 // [g p, (g + 1) p), p = ceil(deg / groups)) is summed in increasing row order;
@@ -723,9 +734,10 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
 #pragma unroll
         for (int e = 0; e < VPT; ++e) {
             if (j[e] >= Z) continue;
-            float L = q[e] * kLog2e;
+            float ps[kVnGroups];
 #pragma unroll
-            for (int g2 = 0; g2 < kVnGroups; ++g2) L += part[g2][v0 + e * kVnLanes];
+            for (int g2 = 0; g2 < kVnGroups; ++g2) ps[g2] = part[g2][v0 + e * kVnLanes];
+            const float L = core_total(q[e], ps);
             at(row, j[e]) = L;
             at(row, j[e] + Z) = L;
         }

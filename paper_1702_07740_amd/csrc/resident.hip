@@ -1,0 +1,396 @@
+// Frame-resident decoder, gfx950: one workgroup decodes one frame for all of
+// its iterations in a single launch, with the frame's whole decode state in
+// LDS.
+//
+// For small liftings the per-iteration launches of the flooding schedule
+// (decoder.hip) are bound by launch latency, not by work: each pass over a
+// code of n = 9,600 takes a few microseconds whatever it computes.  Here a
+// frame's check-to-variable messages, core totals, packed syndrome and
+// degree-1 decision bits live in LDS (160 KB per CU), the iteration loop runs
+// inside the kernel, and the only synchronisation is the workgroup barrier
+// between the check phase (Alg. 1 Step 2, with the Step 4 check of the
+// previous iteration) and the variable phase (Step 3).  Global memory is
+// touched only to read the channel LLRs, to hold the degree-1 inputs Psi
+// (read-only after the first phase), and to write the outputs.
+//
+// The arithmetic is the per-iteration decoder's, operation for operation: the
+// same base-2 state, the same phi2, the same prefix/suffix order of the
+// exclusive sums, the same Phi-domain degree-1 decision, and core totals
+// summed as (Q + S0) + S1 over the same two row groups.  So a frame decodes to
+// the same bits, iteration count and convergence flag on either schedule.
+//
+// Two simplifications against the per-iteration decoder, both exact:
+//  - messages start at zero in LDS, so the first iteration is a steady one
+//    (L_v - 0 = L_v);
+//  - the decision bits of iteration 0 for the degree-1 variables (the channel
+//    signs, in check order) are written once at set-up, so the first
+//    iteration and a zero-iteration decode read them like any other.
+#include "passes.h"
+
+namespace ldpc {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kResThreads = 1024;  // 16 wave64s: four per SIMD of the one CU
+constexpr int kResVnBatch = 8;     // variable phase: blocks loaded together
+
+template <typename Msg>
+struct ResView {
+    Msg *msg;            // [NS][Z] messages, check order (LDS)
+    float *tot;          // [NC][Z] core totals, base 2 (LDS)
+    const uint64_t *syn; // [mb][W] packed syndrome bits (LDS)
+    const float *psi;    // [ND1][Zp] +-Phi(|Q|) of the degree-1 variables, check order (global)
+    unsigned Z, W, Zp;
+};
+
+// Block k of a row is a stored block: DS >= 0 is a compile-time split, DS < 0
+// reads the row's count.
+template <int DS>
+__device__ __forceinline__ bool res_stored(int k, int ns) {
+    if constexpr (DS >= 0) return k < DS;
+    else return k < ns;
+}
+
+// One wave: checks ch*64 + lane of base row r.  D is the row degree (D_MAX
+// with `deg` read at run time for the generic widths).  UPDATE = false only
+// votes.  Returns true if one of the lane's checks fails the parity check of
+// the voted decisions (core: sign of the totals read; degree-1: dprev).
+template <int D, int DS, bool GENERIC, bool UPDATE, typename Msg>
+__device__ __forceinline__ bool res_check(const CodeDev &c, const ResView<Msg> &S, int r,
+                                          unsigned ch, const uint64_t *dprev, uint64_t *dcur,
+                                          const PhiConsts &PK) {
+    const unsigned Z = S.Z, lane = threadIdx.x & 63u;
+    const unsigned a = ch * 64u + lane;
+    const bool valid = a < Z;
+    const unsigned al = valid ? a : Z - 1;
+    const int b0 = uniform_i32(c.row_first + r);
+    const int ns = uniform_i32(c.row_ns + r);
+    const int deg = GENERIC ? uniform_i32(c.row_deg + r) : D;
+    const uint64_t sw = S.syn[(unsigned)r * S.W + ch];
+    float x[D];
+    bool dec[D];
+    unsigned idx[D];  // stored: message index; degree-1: decision-word index
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        x[k] = 0.0f;
+        dec[k] = false;
+        idx[k] = 0;
+        if (GENERIC && k >= deg) continue;
+        const int b = b0 + k;
+        const unsigned s = (unsigned)uniform_i32(c.blk_shift + b);
+        const unsigned ref = (unsigned)uniform_i32(c.blk_ref + b);
+        if (res_stored<DS>(k, ns)) {
+            const unsigned core = (unsigned)uniform_i32(c.blk_core + b);
+            unsigned j = al + s;
+            j -= (j >= Z) ? Z : 0u;
+            const float lt = S.tot[core * Z + j];
+            idx[k] = ref * Z + a;
+            const float mo = UPDATE ? msg_load<Msg>(&S.msg[ref * Z + al]) : 0.0f;
+            x[k] = lt - mo;
+            dec[k] = lt < 0.0f;
+        } else {
+            x[k] = S.psi[ref * S.Zp + al];
+            idx[k] = ref * S.W + ch;
+            dec[k] = (dprev[idx[k]] >> lane) & 1ull;
+        }
+    }
+    bool par = (sw >> lane) & 1ull;
+#pragma unroll
+    for (int k = 0; k < D; ++k) par ^= dec[k];
+    const bool bad = par && valid;
+    if (!UPDATE) return bad;
+
+    // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
+    float ph[D];
+    bool neg[D];
+    bool p2 = (sw >> lane) & 1ull;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        ph[k] = 0.0f;
+        neg[k] = false;
+        if (GENERIC && k >= deg) continue;
+        neg[k] = x[k] < 0.0f;
+        p2 ^= neg[k];
+        ph[k] = res_stored<DS>(k, ns) ? phi2(fabsf(x[k]), PK) : fabsf(x[k]);
+    }
+    float ex[D];
+    if constexpr (GENERIC) {
+        float pre[D];
+        pre[0] = 0.0f;
+#pragma unroll
+        for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + ph[k - 1];
+        float suf = 0.0f;
+#pragma unroll
+        for (int k = D - 1; k >= 0; --k) {
+            ex[k] = 0.0f;
+            if (k >= deg) continue;
+            ex[k] = pre[k] + suf;
+            suf += ph[k];
+        }
+    } else if constexpr (D == 1) {
+        ex[0] = 0.0f;
+    } else {
+        float pre[D];
+        pre[0] = 0.0f;
+#pragma unroll
+        for (int k = 1; k < D; ++k) pre[k] = (k == 1) ? ph[0] : pre[k - 1] + ph[k - 1];
+        float suf = ph[D - 1];
+        ex[D - 1] = pre[D - 1];
+#pragma unroll
+        for (int k = D - 2; k >= 0; --k) {
+            ex[k] = (k == 0) ? suf : pre[k] + suf;
+            suf += ph[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (GENERIC && k >= deg) continue;
+        const bool sgn = p2 ^ neg[k];  // the message to block k is negative
+        if (res_stored<DS>(k, ns)) {
+            const float mag = phi2(ex[k], PK);
+            if (valid) msg_store<Msg>(&S.msg[idx[k]], sgn ? -mag : mag);
+        } else {
+            // degree-1 decision, sign of Q + m, taken in the Phi domain
+            const float Sx = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, PK.hi);
+            const bool d = neg[k] ^ (p2 && !(ph[k] < Sx));
+            const unsigned long long bits = wave_ballot(valid && d);
+            if (lane == 0) dcur[idx[k]] = bits;
+        }
+    }
+    return bad;
+}
+
+// Check phase of one frame: every (row, 64-check chunk) unit, spread over the
+// workgroup's waves.  The row's class picks straight-line code for the common
+// shapes (degree <= 6, at most one degree-1 block) and a generic width
+// otherwise.
+template <bool UPDATE, typename Msg>
+__device__ __forceinline__ bool res_check_phase(const CodeDev &c, const ResView<Msg> &S,
+                                                const uint64_t *dprev, uint64_t *dcur,
+                                                const PhiConsts &PK) {
+    const unsigned nw = blockDim.x >> 6;
+    const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned units = (unsigned)c.mb * S.W;
+    bool bad = false;
+    for (unsigned u = wave; u < units; u += nw) {
+        const int r = (int)(u / S.W);
+        const unsigned ch = u - (unsigned)r * S.W;
+        const int deg = uniform_i32(c.row_deg + r);
+        const int ns = uniform_i32(c.row_ns + r);
+        const bool fixed = deg <= kSmallRowDegree && ns >= deg - 1;
+        const int cls = fixed ? 2 * (deg - 1) + (ns - (deg - 1)) : (deg <= 8 ? 12 : 13);
+#define LDPC_RES(I, D, DS, G) \
+    case I: bad |= res_check<D, DS, G, UPDATE, Msg>(c, S, r, ch, dprev, dcur, PK); break;
+        switch (cls) {
+            LDPC_RES(0, 1, 0, false) LDPC_RES(1, 1, 1, false) LDPC_RES(2, 2, 1, false)
+            LDPC_RES(3, 2, 2, false) LDPC_RES(4, 3, 2, false) LDPC_RES(5, 3, 3, false)
+            LDPC_RES(6, 4, 3, false) LDPC_RES(7, 4, 4, false) LDPC_RES(8, 5, 4, false)
+            LDPC_RES(9, 5, 5, false) LDPC_RES(10, 6, 5, false) LDPC_RES(11, 6, 6, false)
+            LDPC_RES(12, 8, -1, true) LDPC_RES(13, 16, -1, true)
+            default: break;
+        }
+#undef LDPC_RES
+    }
+    return bad;
+}
+
+// Variable phase: L_v = Q_v log2(e) + S0 + S1 per core variable, S0 and S1
+// the sums of the column's first ceil(deg / 2) and remaining blocks, each in
+// increasing row order (the per-iteration decoder's two row groups).
+template <typename Msg>
+__device__ __forceinline__ void res_variable_phase(const CodeDev &c, const ResView<Msg> &S,
+                                                   const float *llr) {
+    const unsigned nw = blockDim.x >> 6;
+    const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned Z = S.Z, units = (unsigned)c.NC * S.W;
+    for (unsigned u = wave; u < units; u += nw) {
+        const int k = (int)(u / S.W);
+        const unsigned j = (u - (unsigned)k * S.W) * 64u + (threadIdx.x & 63u);
+        if (j >= Z) continue;
+        const int deg = uniform_i32(c.core_deg + k);
+        const int per = (deg + kVnGroups - 1) / kVnGroups;
+        const int first = uniform_i32(c.core_first + k);
+        const float q = llr[(size_t)uniform_i32(c.core_col + k) * Z + j];
+        // batches of kResVnBatch blocks: their table and LDS loads issue
+        // together; entries past the group's end add +0, which leaves a sum
+        // that started at +0 unchanged
+        float p[kVnGroups];
+#pragma unroll
+        for (int g = 0; g < kVnGroups; ++g) {
+            p[g] = 0.0f;
+            const int e = min(deg, (g + 1) * per);
+            for (int i0 = g * per; i0 < e; i0 += kResVnBatch) {
+                float xv[kResVnBatch];
+#pragma unroll
+                for (int u2 = 0; u2 < kResVnBatch; ++u2) {
+                    const int i = min(i0 + u2, e - 1);
+                    const unsigned blk = (unsigned)uniform_i32(c.core_state + first + i);
+                    const unsigned s = (unsigned)uniform_i32(c.core_shift + first + i);
+                    const unsigned idx = (j >= s) ? j - s : j + Z - s;
+                    xv[u2] = msg_load<Msg>(&S.msg[blk * Z + idx]);
+                }
+#pragma unroll
+                for (int u2 = 0; u2 < kResVnBatch; ++u2) p[g] += (i0 + u2 < e) ? xv[u2] : 0.0f;
+            }
+        }
+        S.tot[(unsigned)k * Z + j] = core_total(q, p);
+    }
+}
+
+template <typename Msg>
+__global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, ResidentArgs A) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const int f = blockIdx.x;
+    const unsigned Z = (unsigned)c.Z, W = (unsigned)c.W, Zp = (unsigned)c.Zp;
+    ResView<Msg> S;
+    S.msg = reinterpret_cast<Msg *>(lds);
+    S.tot = reinterpret_cast<float *>(lds + A.lds_tot);
+    uint64_t *syn = reinterpret_cast<uint64_t *>(lds + A.lds_syn);
+    S.syn = syn;
+    uint64_t *d1 = reinterpret_cast<uint64_t *>(lds + A.lds_d1);  // [2][ND1][W]
+    int32_t *flag = reinterpret_cast<int32_t *>(lds + A.lds_flag); // [2]
+    float *psi = A.psi + (size_t)f * A.psi_frame;
+    S.psi = psi;
+    S.Z = Z;
+    S.W = W;
+    S.Zp = Zp;
+    const float *llr = A.llr + (size_t)f * c.n;
+    const uint8_t *syn_in = A.syndrome + (size_t)f * c.m;
+    const size_t d1n = (size_t)c.ND1 * W;
+    const unsigned nt = blockDim.x, nw = nt >> 6, lane = threadIdx.x & 63u;
+    const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const PhiConsts PK = phi_consts();
+
+    // Set-up: zero messages, totals of iteration 0, Psi and the channel-sign
+    // decision bits of the degree-1 variables, packed syndrome, vote flags.
+    for (unsigned i = threadIdx.x; i < (unsigned)c.NS * Z; i += nt) msg_store<Msg>(&S.msg[i], 0.0f);
+    for (unsigned i = threadIdx.x; i < (unsigned)c.NC * Z; i += nt) {
+        const unsigned k = i / Z, j = i - k * Z;
+        S.tot[i] = llr[(size_t)c.core_col[k] * Z + j] * kLog2e;
+    }
+    for (unsigned u = wave; u < (unsigned)c.ND1 * W; u += nw) {
+        const unsigned k = u / W, a = (u - k * W) * 64u + lane;
+        bool neg = false;
+        if (a < Z) {
+            unsigned j = a + (unsigned)uniform_i32(c.d1_shift + k);
+            j -= (j >= Z) ? Z : 0u;
+            const float q = llr[(size_t)uniform_i32(c.d1_col + k) * Z + j];
+            const float p = phi2(fabsf(q) * kLog2e, PK);
+            psi[k * Zp + a] = q < 0.0f ? -p : p;
+            neg = q < 0.0f;
+        }
+        const unsigned long long bits = wave_ballot(neg);
+        if (lane == 0) d1[u] = bits;
+    }
+    for (unsigned u = wave; u < (unsigned)c.mb * W; u += nw) {
+        const unsigned r = u / W, a = (u - r * W) * 64u + lane;
+        const bool v = a < Z && (syn_in[(size_t)r * Z + a] & 1);
+        const unsigned long long bits = wave_ballot(v);
+        if (lane == 0) syn[u] = bits;
+    }
+    if (threadIdx.x < 2) flag[threadIdx.x] = 0;
+    __syncthreads();
+
+    const int T = A.T;
+    auto checked = [&](int t) { return t == T || (A.early_stop && t >= A.check_from); };
+    int it = T, conv = 0;
+    bool stopped = false;
+    for (int t = 1; t <= T; ++t) {
+        const bool vote = checked(t - 1);
+        const bool bad = res_check_phase<true, Msg>(c, S, d1 + ((t - 1) & 1) * d1n,
+                                                    d1 + (t & 1) * d1n, PK);
+        if (vote && wave_ballot(bad) != 0ull && lane == 0) flag[t & 1] = 1;
+        __syncthreads();
+        if (vote && flag[t & 1] == 0) {
+            // the decisions of iteration t - 1 satisfy H x = s: stop there
+            it = t - 1;
+            conv = 1;
+            stopped = true;
+            break;
+        }
+        // flag[(t + 1) & 1] was last read before the previous barrier
+        if (threadIdx.x == 0) flag[(t + 1) & 1] = 0;
+        res_variable_phase<Msg>(c, S, llr);
+        __syncthreads();
+    }
+    if (!stopped) {
+        // the check of the last iteration (the channel decisions when T = 0)
+        const bool bad = res_check_phase<false, Msg>(c, S, d1 + (T & 1) * d1n, nullptr, PK);
+        if (wave_ballot(bad) != 0ull && lane == 0) flag[(T + 1) & 1] = 1;
+        __syncthreads();
+        conv = flag[(T + 1) & 1] == 0;
+    }
+
+    // Read-out: decisions at the exit iteration.
+    const uint64_t *dexit = d1 + (it & 1) * d1n;
+    uint8_t *bits_out = A.bits_out + (size_t)f * c.n;
+    for (unsigned v = threadIdx.x; v < (unsigned)c.n; v += nt) {
+        const unsigned col = v / Z, j = v - col * Z;
+        const int kind = c.col_kind[col];
+        const unsigned ref = (unsigned)c.col_ref[col];
+        int bit = llr[v] < 0.0f;
+        if (kind == COL_CORE) {
+            bit = S.tot[ref * Z + j] < 0.0f;
+        } else if (kind == COL_DEG1 && it > 0) {
+            unsigned a = j + Z - (unsigned)c.d1_shift[ref];
+            a -= (a >= Z) ? Z : 0u;
+            bit = (int)((dexit[ref * W + (a >> 6)] >> (a & 63u)) & 1ull);
+        }
+        bits_out[v] = (uint8_t)bit;
+    }
+    if (threadIdx.x == 0) {
+        A.iters_out[f] = it;
+        A.conv_out[f] = (uint8_t)conv;
+    }
+}
+
+}  // namespace
+
+ResidentLayout resident_layout(const CodeDev &c, bool fp16) {
+    auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    ResidentLayout L{};
+    L.tot = a16((size_t)c.NS * c.Z * (fp16 ? 2 : 4));
+    L.syn = a16(L.tot + (size_t)c.NC * c.Z * 4);
+    L.d1 = L.syn + (size_t)c.mb * c.W * 8;
+    L.flag = L.d1 + 2 * (size_t)c.ND1 * c.W * 8;
+    L.total = a16(L.flag + 2 * 4);
+    return L;
+}
+
+hipError_t enqueue_resident(const DecodeLaunch &l, const WorkLayout &W, size_t lds_limit) {
+    const CodeDev &c = l.c;
+    const ResidentLayout R = resident_layout(c, l.fp16 != 0);
+    if (R.total > lds_limit) return hipErrorInvalidValue;
+    ResidentArgs a{};
+    a.llr = l.llr;
+    a.syndrome = l.syndrome;
+    a.psi = reinterpret_cast<float *>(l.ws + W.psi);
+    a.bits_out = l.bits_out;
+    a.iters_out = l.iters_out;
+    a.conv_out = l.conv_out;
+    a.psi_frame = W.psi_frame;
+    a.T = l.T;
+    a.early_stop = l.early_stop;
+    a.check_from = l.check_from;
+    a.lds_tot = (unsigned)R.tot;
+    a.lds_syn = (unsigned)R.syn;
+    a.lds_d1 = (unsigned)R.d1;
+    a.lds_flag = (unsigned)R.flag;
+    const dim3 grid((unsigned)l.F), block(kResThreads);
+    if (l.fp16) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(resident_decode<_Float16>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)R.total);
+        if (e != hipSuccess) return e;
+        resident_decode<_Float16><<<grid, block, R.total, l.stream>>>(c, a);
+    } else {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(resident_decode<float>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)R.total);
+        if (e != hipSuccess) return e;
+        resident_decode<float><<<grid, block, R.total, l.stream>>>(c, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ldpc

@@ -28,8 +28,11 @@ EXPORTS = (
     "ldpc_workspace_bytes", "ldpc_decode_batch", "ldpc_syndrome", "ldpc_status_string",
     "ldpc_last_error", "ldpc_reconciliation_llr", "ldpc_reconciliation_message",
     "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_request_bytes", "ldpc_engine_submit",
-    "ldpc_engine_step", "ldpc_engine_poll",
+    "ldpc_engine_step", "ldpc_engine_poll", "ldpc_decode_schedule",
 )
+
+SCHEDULE_AUTO, SCHEDULE_LAUNCHES, SCHEDULE_RESIDENT = 0, 1, 2
+_SCHEDULES = {"auto": SCHEDULE_AUTO, "launches": SCHEDULE_LAUNCHES, "resident": SCHEDULE_RESIDENT}
 
 
 class LdpcError(RuntimeError):
@@ -54,6 +57,7 @@ class DecodeOpts(ctypes.Structure):
         ("msg_fp16", ctypes.c_int32), ("checks_per_thread", ctypes.c_int32),
         ("llr_out", ctypes.c_void_p),
         ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
     ]
 
 
@@ -93,6 +97,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.ldpc_decode_batch.restype = ctypes.c_int
         lib.ldpc_decode_batch.argtypes = [P, I32, P, P, I32, P, P, P,
                                           ctypes.POINTER(DecodeOpts), P, ctypes.c_size_t, P]
+        lib.ldpc_decode_schedule.restype = ctypes.c_int
+        lib.ldpc_decode_schedule.argtypes = [P, I32, ctypes.POINTER(DecodeOpts), ctypes.POINTER(I32)]
         lib.ldpc_syndrome.restype = ctypes.c_int
         lib.ldpc_syndrome.argtypes = [P, I32, P, P, P]
         lib.ldpc_status_string.restype = ctypes.c_char_p
@@ -137,10 +143,11 @@ def _stream_handle(stream):
 
 
 def make_opts(early_stop=True, check_from_iter=0, msg_fp16=False, llr_out_ptr=None,
-              timing_events=None, checks_per_thread=0) -> DecodeOpts:
+              timing_events=None, checks_per_thread=0, schedule="auto") -> DecodeOpts:
     o = DecodeOpts()
     load().ldpc_decode_opts_init(ctypes.byref(o))
     o.checks_per_thread = int(checks_per_thread)
+    o.schedule = _SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.early_stop = int(bool(early_stop))
     o.check_from_iter = int(check_from_iter)
     o.msg_fp16 = int(bool(msg_fp16))
@@ -196,9 +203,22 @@ class Code:
         off = (-ws.data_ptr()) % 256
         return ws[off:off + nbytes]
 
+    def schedule(self, F=1, msg_fp16=False, want_llr=False, timing=False, schedule="auto") -> str:
+        """The schedule ("launches" or "resident") a decode of F frames with these options runs on."""
+        o = make_opts(msg_fp16=msg_fp16, schedule=schedule)
+        if want_llr:
+            o.llr_out = ctypes.c_void_p(1)  # only tested for null
+        if timing:
+            o.timing_events = (ctypes.c_void_p * 1)()
+            o.n_timing_events = 1
+        out = ctypes.c_int32()
+        _check(load().ldpc_decode_schedule(self._h, int(F), ctypes.byref(o), ctypes.byref(out)),
+               "ldpc_decode_schedule")
+        return {SCHEDULE_LAUNCHES: "launches", SCHEDULE_RESIDENT: "resident"}[out.value]
+
     def decode(self, llr, syndrome, max_iters: int, early_stop=True, check_from_iter=0,
                msg_fp16=False, want_llr=False, workspace=None, out=None, stream=None,
-               timing_events=None, checks_per_thread=0):
+               timing_events=None, checks_per_thread=0, schedule="auto"):
         """Decode frames llr [F][n] float32 / syndrome [F][m] uint8 (CUDA tensors).
 
         Returns (bits uint8 [F][n], iters int32 [F], converged uint8 [F], L or None),
@@ -226,7 +246,7 @@ class Code:
             workspace = self.alloc_workspace(F, max_iters, msg_fp16, want_llr, dev)
         opts = make_opts(early_stop, check_from_iter, msg_fp16,
                          L.data_ptr() if L is not None else None, timing_events,
-                         checks_per_thread)
+                         checks_per_thread, schedule)
         st = load().ldpc_decode_batch(
             self._h, F, llr.data_ptr(), syndrome.data_ptr(), int(max_iters),
             bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ctypes.byref(opts),

@@ -353,7 +353,8 @@ def test_timing_events(ldpc, oracle_mod):
     ev.close()
 
 
-def test_decode_replays_from_a_captured_graph(ldpc, oracle_mod):
+@pytest.mark.parametrize("schedule", ["launches", "resident"])
+def test_decode_replays_from_a_captured_graph(ldpc, oracle_mod, schedule):
     """A whole decode (caller-owned workspace and outputs) captured by stream
     capture replays bit-identically, several times, with eager work between
     the replays (the graph holds kernels only: no memset or copy nodes)."""
@@ -368,17 +369,17 @@ def test_decode_replays_from_a_captured_graph(ldpc, oracle_mod):
     out = (torch.empty((F, g.n), dtype=torch.uint8, device="cuda"),
            torch.empty(F, dtype=torch.int32, device="cuda"),
            torch.empty(F, dtype=torch.uint8, device="cuda"), None)
-    _say("graph capture", Z, F, T)
-    g.decode(dQ, ds, T, workspace=ws, out=out)
+    _say("graph capture", Z, F, T, schedule)
+    g.decode(dQ, ds, T, workspace=ws, out=out, schedule=schedule)
     torch.cuda.synchronize()
     ref = [t.cpu().clone() for t in out[:3]]
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.stream(side):
-        g.decode(dQ, ds, T, workspace=ws, out=out)
+        g.decode(dQ, ds, T, workspace=ws, out=out, schedule=schedule)
         with torch.cuda.graph(graph, stream=side):
-            g.decode(dQ, ds, T, workspace=ws, out=out)
+            g.decode(dQ, ds, T, workspace=ws, out=out, schedule=schedule)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     for rep in range(3):
