@@ -255,6 +255,44 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
             core_tab[(size_t)k * tab_stride + 2 * i + 1] = core_shift[core_first[k] + i];
         }
     const size_t o_ct = put(core_tab);
+    // the same tables in the frame-resident schedule's LDS layout (stride Z)
+    std::vector<int32_t> res_desc((size_t)mb * ldpc::kResDescWords, 0);
+    for (int r = 0; r < mb; ++r) {
+        int32_t *dd = &res_desc[(size_t)r * ldpc::kResDescWords];
+        dd[0] = common(r) ? cls_of(r) : (row_deg[r] <= 8 ? 12 : 13);
+        dd[1] = row_deg[r];
+        dd[2] = row_ns[r];
+        dd[3] = row_first[r];
+        dd[4] = r * W;
+        if (!common(r)) continue;
+        for (int k = 0; k < row_deg[r]; ++k) {
+            const int b = row_first[r] + k;
+            const bool st = k < row_ns[r];
+            dd[5 + k] = st ? blk_core[b] * Z : blk_ref[b] * Zp;
+            dd[11 + k] = st ? blk_ref[b] * Z : blk_ref[b] * W;
+            dd[17 + k] = blk_shift[b];
+        }
+    }
+    const size_t o_resd = put(res_desc);
+    // rows padded to whole batches of 8 pairs, plus one batch of slack, so a
+    // batch read from any in-range start stays inside the table
+    const int res_stride = (tab_stride + 15) / 16 * 16;
+    std::vector<int32_t> res_core((size_t)std::max(NC, 1) * res_stride + 16, 0);
+    for (int k = 0; k < NC; ++k)
+        for (int i = 0; i < core_deg[k]; ++i) {
+            res_core[(size_t)k * res_stride + 2 * i] = core_state[core_first[k] + i] * Z;
+            res_core[(size_t)k * res_stride + 2 * i + 1] = core_shift[core_first[k] + i];
+        }
+    const size_t o_resc = put(res_core);
+    // check-phase units in class order (only where a frame could fit in LDS:
+    // at most 2^16 units)
+    std::vector<int32_t> res_unit;
+    if ((int64_t)mb * W <= (1 << 16)) {
+        for (int y = 0; y < mb; ++y)
+            for (int ch = 0; ch < W; ++ch) res_unit.push_back(row_list[y] | (ch << 16));
+    }
+    const int32_t n_res_units = (int32_t)res_unit.size();
+    const size_t o_resu = put(res_unit);
 
     ldpc_code *code = new (std::nothrow) ldpc_code();
     if (!code) return fail_with(LDPC_ENOMEM, "host allocation failed");
@@ -317,6 +355,11 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.core_shift = T + o_csh;
     d.core_tab = T + o_ct;
     d.core_tab_stride = tab_stride;
+    d.res_desc = T + o_resd;
+    d.res_core = T + o_resc;
+    d.res_core_stride = res_stride;
+    d.res_unit = T + o_resu;
+    d.res_units = n_res_units;
     d.col_kind = T + o_colk;
     d.col_ref = T + o_colr;
     d.d1_shift = T + o_d1s;
@@ -395,7 +438,7 @@ int resolve_schedule(const ldpc_code *code, int F, const ldpc_decode_opts &o, in
                          o.checks_per_thread);
     if (o.schedule < LDPC_SCHEDULE_AUTO || o.schedule > LDPC_SCHEDULE_RESIDENT)
         return fail_with(LDPC_EINVAL, "schedule = %d is not 0, 1 or 2", o.schedule);
-    const bool possible = !o.llr_out && !o.timing_events &&
+    const bool possible = !o.llr_out && !o.timing_events && code->dev.res_units > 0 &&
                           ldpc::resident_layout(code->dev, o.msg_fp16 != 0).total <= code->lds_limit;
     if (o.schedule == LDPC_SCHEDULE_RESIDENT && !possible)
         return fail_with(LDPC_EUNSUPPORTED,

@@ -32,6 +32,10 @@ constexpr int kFixedClasses = 2 * kSmallRowDegree;
 // Words of a common row's descriptor (see CodeDev::row_desc).
 constexpr int kRowDescWords = 20;
 
+// Words of a row's descriptor for the frame-resident schedule (see
+// CodeDev::res_desc).
+constexpr int kResDescWords = 24;
+
 // Default and largest checks per thread of the common-row check kernel.
 constexpr int kDefaultChecksPerThread = 4;
 constexpr int kMaxChecksPerThread = 4;
@@ -88,6 +92,25 @@ struct CodeDev {
     // without loading core_first first
     const int32_t *core_tab;
     int32_t core_tab_stride;
+    // frame-resident schedule (offsets into a frame's LDS arrays, Z per block):
+    // per base row r, kResDescWords words at r * kResDescWords:
+    //   0 class (0..11 common classes as above, 12 / 13 other rows of degree
+    //     <= 8 / <= 16), 1 degree, 2 stored blocks, 3 first block, 4 r * W
+    //   [5, 11)  common rows, block k: stored: core * Z (totals), degree-1:
+    //            index * Zp (Psi)
+    //   [11, 17) stored: state index * Z (messages), degree-1: index * W
+    //            (decision words)
+    //   [17, 23) shift of block k
+    // and per core column k, at res_core[k * res_core_stride], its blocks as
+    // (state index * Z, shift) pairs in increasing row order (rows padded with
+    // zero pairs to a multiple of 8 pairs, and 8 more pairs after the last)
+    const int32_t *res_desc, *res_core;
+    int32_t res_core_stride;
+    // the check-phase units (base row r, chunk ch of 64 checks) as r | ch << 16,
+    // rows in class order; res_units = mb * W, or 0 where the schedule is not
+    // offered (a table that large would never fit LDS)
+    const int32_t *res_unit;
+    int32_t res_units;
     int32_t max_core_deg;  // largest degree of a core column
     // per base column: kind and index within its kind
     const int32_t *col_kind, *col_ref;

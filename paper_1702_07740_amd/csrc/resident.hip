@@ -53,39 +53,140 @@ __device__ __forceinline__ bool res_stored(int k, int ns) {
     else return k < ns;
 }
 
-// One wave: checks ch*64 + lane of base row r.  D is the row degree (D_MAX
-// with `deg` read at run time for the generic widths).  UPDATE = false only
-// votes.  Returns true if one of the lane's checks fails the parity check of
-// the voted decisions (core: sign of the totals read; degree-1: dprev).
-template <int D, int DS, bool GENERIC, bool UPDATE, typename Msg>
-__device__ __forceinline__ bool res_check(const CodeDev &c, const ResView<Msg> &S, int r,
-                                          unsigned ch, const uint64_t *dprev, uint64_t *dcur,
-                                          const PhiConsts &PK) {
+// Exclusive Phi sums of a check's inputs, in the order of the per-iteration
+// decoder: prefix sums from the left, suffix sums from the right.
+template <int D>
+__device__ __forceinline__ void res_exclusive(const float (&ph)[D], float (&ex)[D]) {
+    if constexpr (D == 1) {
+        ex[0] = 0.0f;
+    } else {
+        float pre[D];
+        pre[0] = 0.0f;
+#pragma unroll
+        for (int k = 1; k < D; ++k) pre[k] = (k == 1) ? ph[0] : pre[k - 1] + ph[k - 1];
+        float suf = ph[D - 1];
+        ex[D - 1] = pre[D - 1];
+#pragma unroll
+        for (int k = D - 2; k >= 0; --k) {
+            ex[k] = (k == 0) ? suf : pre[k] + suf;
+            suf += ph[k];
+        }
+    }
+}
+
+// K units of a common row class (degree D, DS stored blocks, then one
+// degree-1 block if DS < D): for each q < K, checks ch[q]*64 + lane of the
+// row whose resident descriptor is d[q].  The K units' loads issue together,
+// so a wave has K independent chains in flight.  UPDATE = false only votes.
+// Returns true if one of the lane's checks fails the parity check of the
+// voted decisions (core: sign of the totals read; degree-1: dprev).
+template <int D, int DS, bool UPDATE, typename Msg, int K>
+__device__ __forceinline__ bool res_fixed(const ResView<Msg> &S, const int32_t *const (&d)[K],
+                                          const unsigned (&ch)[K], const uint64_t *dprev,
+                                          uint64_t *dcur, const PhiConsts &PK) {
+    const unsigned Z = S.Z, lane = threadIdx.x & 63u;
+    float x[K][D];
+    bool dec[K][D];
+    unsigned idx[K][D];  // stored: message index; degree-1: decision-word index
+    uint64_t sw[K];
+    bool valid[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const unsigned a = ch[q] * 64u + lane;
+        valid[q] = a < Z;
+        const unsigned al = valid[q] ? a : Z - 1;
+        sw[q] = S.syn[(unsigned)uniform_i32(d[q] + 4) + ch[q]];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const unsigned s = (unsigned)uniform_i32(d[q] + 17 + k);
+            const unsigned o0 = (unsigned)uniform_i32(d[q] + 5 + k);
+            const unsigned o1 = (unsigned)uniform_i32(d[q] + 11 + k);
+            if (k < DS) {
+                unsigned j = al + s;
+                j -= (j >= Z) ? Z : 0u;
+                const float lt = S.tot[o0 + j];
+                idx[q][k] = o1 + a;
+                const float mo = UPDATE ? msg_load<Msg>(&S.msg[o1 + al]) : 0.0f;
+                x[q][k] = lt - mo;
+                dec[q][k] = lt < 0.0f;
+            } else {
+                x[q][k] = S.psi[o0 + al];
+                idx[q][k] = o1 + ch[q];
+                dec[q][k] = (dprev[idx[q][k]] >> lane) & 1ull;
+            }
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        bool par = (sw[q] >> lane) & 1ull;
+#pragma unroll
+        for (int k = 0; k < D; ++k) par ^= dec[q][k];
+        bad |= par && valid[q];
+    }
+    if (!UPDATE) return bad;
+
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
+        float ph[D], ex[D];
+        bool neg[D];
+        bool p2 = (sw[q] >> lane) & 1ull;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            neg[k] = x[q][k] < 0.0f;
+            p2 ^= neg[k];
+            ph[k] = (k < DS) ? phi2(fabsf(x[q][k]), PK) : fabsf(x[q][k]);
+        }
+        res_exclusive<D>(ph, ex);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const bool sgn = p2 ^ neg[k];  // the message to block k is negative
+            if (k < DS) {
+                const float mag = phi2(ex[k], PK);
+                if (valid[q]) msg_store<Msg>(&S.msg[idx[q][k]], sgn ? -mag : mag);
+            } else {
+                // degree-1 decision, sign of Q + m, taken in the Phi domain
+                const float Sx = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, PK.hi);
+                const bool dd = neg[k] ^ (p2 && !(ph[k] < Sx));
+                const unsigned long long bits = wave_ballot(valid[q] && dd);
+                if (lane == 0) dcur[idx[q][k]] = bits;
+            }
+        }
+    }
+    return bad;
+}
+
+// One unit of any other row (degree up to D, stored count and degree read at
+// run time), offsets from the block tables; same arithmetic as above.
+template <int D, bool UPDATE, typename Msg>
+__device__ __forceinline__ bool res_generic(const CodeDev &c, const ResView<Msg> &S,
+                                            const int32_t *d, unsigned ch, const uint64_t *dprev,
+                                            uint64_t *dcur, const PhiConsts &PK) {
     const unsigned Z = S.Z, lane = threadIdx.x & 63u;
     const unsigned a = ch * 64u + lane;
     const bool valid = a < Z;
     const unsigned al = valid ? a : Z - 1;
-    const int b0 = uniform_i32(c.row_first + r);
-    const int ns = uniform_i32(c.row_ns + r);
-    const int deg = GENERIC ? uniform_i32(c.row_deg + r) : D;
-    const uint64_t sw = S.syn[(unsigned)r * S.W + ch];
+    const int deg = uniform_i32(d + 1);
+    const int ns = uniform_i32(d + 2);
+    const int b0 = uniform_i32(d + 3);
+    const uint64_t sw = S.syn[(unsigned)uniform_i32(d + 4) + ch];
     float x[D];
     bool dec[D];
-    unsigned idx[D];  // stored: message index; degree-1: decision-word index
+    unsigned idx[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         x[k] = 0.0f;
         dec[k] = false;
         idx[k] = 0;
-        if (GENERIC && k >= deg) continue;
+        if (k >= deg) continue;
         const int b = b0 + k;
         const unsigned s = (unsigned)uniform_i32(c.blk_shift + b);
         const unsigned ref = (unsigned)uniform_i32(c.blk_ref + b);
-        if (res_stored<DS>(k, ns)) {
-            const unsigned core = (unsigned)uniform_i32(c.blk_core + b);
+        if (k < ns) {
             unsigned j = al + s;
             j -= (j >= Z) ? Z : 0u;
-            const float lt = S.tot[core * Z + j];
+            const float lt = S.tot[(unsigned)uniform_i32(c.blk_core + b) * Z + j];
             idx[k] = ref * Z + a;
             const float mo = UPDATE ? msg_load<Msg>(&S.msg[ref * Z + al]) : 0.0f;
             x[k] = lt - mo;
@@ -102,7 +203,6 @@ __device__ __forceinline__ bool res_check(const CodeDev &c, const ResView<Msg> &
     const bool bad = par && valid;
     if (!UPDATE) return bad;
 
-    // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
     float ph[D];
     bool neg[D];
     bool p2 = (sw >> lane) & 1ull;
@@ -110,88 +210,96 @@ __device__ __forceinline__ bool res_check(const CodeDev &c, const ResView<Msg> &
     for (int k = 0; k < D; ++k) {
         ph[k] = 0.0f;
         neg[k] = false;
-        if (GENERIC && k >= deg) continue;
+        if (k >= deg) continue;
         neg[k] = x[k] < 0.0f;
         p2 ^= neg[k];
-        ph[k] = res_stored<DS>(k, ns) ? phi2(fabsf(x[k]), PK) : fabsf(x[k]);
+        ph[k] = (k < ns) ? phi2(fabsf(x[k]), PK) : fabsf(x[k]);
     }
+    // exclusive sums over the first deg entries: the same additions as the
+    // fixed-degree form (adding the initial 0 is exact)
     float ex[D];
-    if constexpr (GENERIC) {
-        float pre[D];
-        pre[0] = 0.0f;
+    float pre[D];
+    pre[0] = 0.0f;
 #pragma unroll
-        for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + ph[k - 1];
-        float suf = 0.0f;
+    for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + ph[k - 1];
+    float suf = 0.0f;
 #pragma unroll
-        for (int k = D - 1; k >= 0; --k) {
-            ex[k] = 0.0f;
-            if (k >= deg) continue;
-            ex[k] = pre[k] + suf;
-            suf += ph[k];
-        }
-    } else if constexpr (D == 1) {
-        ex[0] = 0.0f;
-    } else {
-        float pre[D];
-        pre[0] = 0.0f;
-#pragma unroll
-        for (int k = 1; k < D; ++k) pre[k] = (k == 1) ? ph[0] : pre[k - 1] + ph[k - 1];
-        float suf = ph[D - 1];
-        ex[D - 1] = pre[D - 1];
-#pragma unroll
-        for (int k = D - 2; k >= 0; --k) {
-            ex[k] = (k == 0) ? suf : pre[k] + suf;
-            suf += ph[k];
-        }
+    for (int k = D - 1; k >= 0; --k) {
+        ex[k] = 0.0f;
+        if (k >= deg) continue;
+        ex[k] = pre[k] + suf;
+        suf += ph[k];
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        if (GENERIC && k >= deg) continue;
-        const bool sgn = p2 ^ neg[k];  // the message to block k is negative
-        if (res_stored<DS>(k, ns)) {
+        if (k >= deg) continue;
+        const bool sgn = p2 ^ neg[k];
+        if (k < ns) {
             const float mag = phi2(ex[k], PK);
             if (valid) msg_store<Msg>(&S.msg[idx[k]], sgn ? -mag : mag);
         } else {
-            // degree-1 decision, sign of Q + m, taken in the Phi domain
             const float Sx = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, PK.hi);
-            const bool d = neg[k] ^ (p2 && !(ph[k] < Sx));
-            const unsigned long long bits = wave_ballot(valid && d);
+            const bool dd = neg[k] ^ (p2 && !(ph[k] < Sx));
+            const unsigned long long bits = wave_ballot(valid && dd);
             if (lane == 0) dcur[idx[k]] = bits;
         }
     }
     return bad;
 }
 
-// Check phase of one frame: every (row, 64-check chunk) unit, spread over the
-// workgroup's waves.  The row's class picks straight-line code for the common
-// shapes (degree <= 6, at most one degree-1 block) and a generic width
-// otherwise.
+// One unit (row descriptor d, chunk ch) of any class.
+template <bool UPDATE, typename Msg>
+__device__ __forceinline__ bool res_unit(const CodeDev &c, const ResView<Msg> &S, int cls,
+                                         const int32_t *d, unsigned ch, const uint64_t *dprev,
+                                         uint64_t *dcur, const PhiConsts &PK) {
+    const int32_t *const dv[1] = {d};
+    const unsigned cv[1] = {ch};
+#define LDPC_RES(I, D, DS) \
+    case I: return res_fixed<D, DS, UPDATE, Msg, 1>(S, dv, cv, dprev, dcur, PK);
+    switch (cls) {
+        LDPC_RES(0, 1, 0) LDPC_RES(1, 1, 1) LDPC_RES(2, 2, 1) LDPC_RES(3, 2, 2)
+        LDPC_RES(4, 3, 2) LDPC_RES(5, 3, 3) LDPC_RES(6, 4, 3) LDPC_RES(7, 4, 4)
+        LDPC_RES(8, 5, 4) LDPC_RES(9, 5, 5) LDPC_RES(10, 6, 5) LDPC_RES(11, 6, 6)
+        case 12: return res_generic<8, UPDATE, Msg>(c, S, d, ch, dprev, dcur, PK);
+        case 13: return res_generic<16, UPDATE, Msg>(c, S, d, ch, dprev, dcur, PK);
+        default: return false;
+    }
+#undef LDPC_RES
+}
+
+// Check phase of one frame.  The units (row, chunk of 64 checks) are listed
+// with the rows in class order; the waves take pairs of consecutive units in
+// turn, and a pair of one common class runs as one two-unit chain.
 template <bool UPDATE, typename Msg>
 __device__ __forceinline__ bool res_check_phase(const CodeDev &c, const ResView<Msg> &S,
                                                 const uint64_t *dprev, uint64_t *dcur,
                                                 const PhiConsts &PK) {
-    const unsigned nw = blockDim.x >> 6;
-    const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const unsigned units = (unsigned)c.mb * S.W;
+    const int nw = (int)(blockDim.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int units = c.res_units;
     bool bad = false;
-    for (unsigned u = wave; u < units; u += nw) {
-        const int r = (int)(u / S.W);
-        const unsigned ch = u - (unsigned)r * S.W;
-        const int deg = uniform_i32(c.row_deg + r);
-        const int ns = uniform_i32(c.row_ns + r);
-        const bool fixed = deg <= kSmallRowDegree && ns >= deg - 1;
-        const int cls = fixed ? 2 * (deg - 1) + (ns - (deg - 1)) : (deg <= 8 ? 12 : 13);
-#define LDPC_RES(I, D, DS, G) \
-    case I: bad |= res_check<D, DS, G, UPDATE, Msg>(c, S, r, ch, dprev, dcur, PK); break;
-        switch (cls) {
-            LDPC_RES(0, 1, 0, false) LDPC_RES(1, 1, 1, false) LDPC_RES(2, 2, 1, false)
-            LDPC_RES(3, 2, 2, false) LDPC_RES(4, 3, 2, false) LDPC_RES(5, 3, 3, false)
-            LDPC_RES(6, 4, 3, false) LDPC_RES(7, 4, 4, false) LDPC_RES(8, 5, 4, false)
-            LDPC_RES(9, 5, 5, false) LDPC_RES(10, 6, 5, false) LDPC_RES(11, 6, 6, false)
-            LDPC_RES(12, 8, -1, true) LDPC_RES(13, 16, -1, true)
-            default: break;
+    for (int u = 2 * wave; u < units; u += 2 * nw) {
+        const bool two = u + 1 < units;
+        const int32_t pk0 = uniform_i32(c.res_unit + u);
+        const int32_t pk1 = uniform_i32(c.res_unit + (two ? u + 1 : u));
+        const int32_t *const d[2] = {c.res_desc + (size_t)(pk0 & 0xffff) * kResDescWords,
+                                     c.res_desc + (size_t)(pk1 & 0xffff) * kResDescWords};
+        const unsigned ch[2] = {(unsigned)pk0 >> 16, (unsigned)pk1 >> 16};
+        const int cls0 = uniform_i32(d[0]), cls1 = uniform_i32(d[1]);
+        if (two && cls0 == cls1 && cls0 < kFixedClasses) {
+#define LDPC_RES2(I, D, DS) \
+    case I: bad |= res_fixed<D, DS, UPDATE, Msg, 2>(S, d, ch, dprev, dcur, PK); break;
+            switch (cls0) {
+                LDPC_RES2(0, 1, 0) LDPC_RES2(1, 1, 1) LDPC_RES2(2, 2, 1) LDPC_RES2(3, 2, 2)
+                LDPC_RES2(4, 3, 2) LDPC_RES2(5, 3, 3) LDPC_RES2(6, 4, 3) LDPC_RES2(7, 4, 4)
+                LDPC_RES2(8, 5, 4) LDPC_RES2(9, 5, 5) LDPC_RES2(10, 6, 5) LDPC_RES2(11, 6, 6)
+                default: break;
+            }
+#undef LDPC_RES2
+        } else {
+            bad |= res_unit<UPDATE, Msg>(c, S, cls0, d[0], ch[0], dprev, dcur, PK);
+            if (two) bad |= res_unit<UPDATE, Msg>(c, S, cls1, d[1], ch[1], dprev, dcur, PK);
         }
-#undef LDPC_RES
     }
     return bad;
 }
@@ -211,11 +319,12 @@ __device__ __forceinline__ void res_variable_phase(const CodeDev &c, const ResVi
         if (j >= Z) continue;
         const int deg = uniform_i32(c.core_deg + k);
         const int per = (deg + kVnGroups - 1) / kVnGroups;
-        const int first = uniform_i32(c.core_first + k);
+        const int32_t *tab = c.res_core + (size_t)k * c.res_core_stride;
         const float q = llr[(size_t)uniform_i32(c.core_col + k) * Z + j];
-        // batches of kResVnBatch blocks: their table and LDS loads issue
-        // together; entries past the group's end add +0, which leaves a sum
-        // that started at +0 unchanged
+        // batches of kResVnBatch blocks: one burst of table loads, then their
+        // LDS loads together.  Entries past the group's end (the next group's,
+        // or zero padding: valid offsets either way) add +0, which leaves a
+        // sum that started at +0 unchanged.
         float p[kVnGroups];
 #pragma unroll
         for (int g = 0; g < kVnGroups; ++g) {
@@ -225,11 +334,10 @@ __device__ __forceinline__ void res_variable_phase(const CodeDev &c, const ResVi
                 float xv[kResVnBatch];
 #pragma unroll
                 for (int u2 = 0; u2 < kResVnBatch; ++u2) {
-                    const int i = min(i0 + u2, e - 1);
-                    const unsigned blk = (unsigned)uniform_i32(c.core_state + first + i);
-                    const unsigned s = (unsigned)uniform_i32(c.core_shift + first + i);
+                    const unsigned off = (unsigned)uniform_i32(tab + 2 * (i0 + u2));
+                    const unsigned s = (unsigned)uniform_i32(tab + 2 * (i0 + u2) + 1);
                     const unsigned idx = (j >= s) ? j - s : j + Z - s;
-                    xv[u2] = msg_load<Msg>(&S.msg[blk * Z + idx]);
+                    xv[u2] = msg_load<Msg>(&S.msg[off + idx]);
                 }
 #pragma unroll
                 for (int u2 = 0; u2 < kResVnBatch; ++u2) p[g] += (i0 + u2 < e) ? xv[u2] : 0.0f;
