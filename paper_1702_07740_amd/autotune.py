@@ -1,11 +1,17 @@
-"""Schedule autotuner for the check kernel.
+"""Schedule autotuner for the decoder.
 
-The tunable is checks per thread (1, 2 or 4): how many checks of a base row
-one thread handles, i.e. how many wavefronts cover one circulant block.  More
-checks per thread amortise the row's table reads and keep more loads in flight
-per thread; fewer give more workgroups for small Z and few frames.  Results do
-not depend on the choice (the arithmetic per check is identical), so the
-tuner only measures time: each candidate decodes the actual batch for a few
+Tunables:
+- checks per thread (1, 2 or 4) of the per-iteration check kernel: how many
+  checks of a base row one thread handles, i.e. how many wavefronts cover one
+  circulant block.  More checks per thread amortise the row's table reads and
+  keep more loads in flight per thread; fewer give more workgroups for small Z
+  and few frames;
+- for a single decode call, also the schedule: per-iteration launches or the
+  frame-resident kernel (one workgroup per frame, state in LDS), where the
+  code's state fits.
+
+Results do not depend on the choice (the arithmetic is identical), so the tuner
+only measures time: each candidate decodes the actual batch for a few
 iterations with early stop off, timed with HIP events, and the fastest wins.
 Choices are cached in a JSON file keyed by the workload's shape, precision and
 device name (LDPC_AUTOTUNE_CACHE overrides the path).
@@ -72,19 +78,31 @@ def _time(fn, reps=3):
 
 
 def tune_decode(code, llr, syndrome, msg_fp16=False, iters=8, use_cache=True):
-    """Best checks_per_thread for ldpc_decode_batch on this batch; (best, {cpt: ms})."""
-    key = _key("decode", [_shape(code, llr.shape[0])], msg_fp16)
+    """Best decode configuration for ldpc_decode_batch on this batch.
+
+    Returns (best, ms): best = {"schedule": "launches" | "resident",
+    "checks_per_thread": 1 | 2 | 4 (0 for the resident schedule)}, ms = the time
+    of each candidate, keyed "launches/<cpt>" or "resident".
+    """
+    from paper_1702_07740_amd import ldpc
+    key = _key("decode2", [_shape(code, llr.shape[0])], msg_fp16)
     if use_cache:
         hit = _load_cache().get(key)
         if hit:
             return hit["best"], hit["ms"]
     ws = code.alloc_workspace(llr.shape[0], iters, msg_fp16=msg_fp16)
+    cands = {f"launches/{cpt}": {"schedule": "launches", "checks_per_thread": cpt}
+             for cpt in CANDIDATES}
+    try:
+        code.schedule(F=llr.shape[0], msg_fp16=msg_fp16, schedule="resident")
+        cands["resident"] = {"schedule": "resident", "checks_per_thread": 0}
+    except ldpc.LdpcError:
+        pass  # the frame's state does not fit one workgroup's LDS
     ms = {}
-    for cpt in CANDIDATES:
-        ms[cpt] = _time(lambda: code.decode(llr, syndrome, iters, early_stop=False,
-                                            msg_fp16=msg_fp16, workspace=ws,
-                                            checks_per_thread=cpt))
-    best = min(ms, key=ms.get)
+    for name, cfg in cands.items():
+        ms[name] = _time(lambda: code.decode(llr, syndrome, iters, early_stop=False,
+                                             msg_fp16=msg_fp16, workspace=ws, **cfg))
+    best = cands[min(ms, key=ms.get)]
     _store(key, {"best": best, "ms": ms})
     return best, ms
 

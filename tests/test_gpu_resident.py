@@ -189,3 +189,27 @@ def test_many_frames(ldpc, oracle_mod):
     s = o.syndrome(x)
     _say("resident many frames", F)
     _same(g, Q, s, 50)
+
+
+def test_autotuner_picks_the_fastest_schedule(ldpc, oracle_mod, tmp_path, monkeypatch):
+    """The autotuner times every (schedule, checks per thread) candidate on the
+    actual batch and returns the fastest; its choice decodes identically."""
+    from paper_1702_07740_amd import autotune
+    monkeypatch.setenv("LDPC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    Z, F = 64, 128
+    base = synth.template_base(144, Z, seed=1)
+    g, o = ldpc.Code(base, Z), oracle_mod.OracleCode(base, Z)
+    x, Q = synth.biawgn_frames(o.n, F, -13.5, seed=128)
+    s = o.syndrome(x)
+    dQ, ds = _dev(Q), _dev(s)
+    _say("autotune schedule", Z, F)
+    best, ms = autotune.tune_decode(g, dQ, ds)
+    assert set(ms) == {"launches/1", "launches/2", "launches/4", "resident"}
+    name = "resident" if best["schedule"] == "resident" else f"launches/{best['checks_per_thread']}"
+    assert ms[name] == min(ms.values())
+    again, _ = autotune.tune_decode(g, dQ, ds)  # from the cache
+    assert again == best
+    ref = _run(g, Q, s, 50, schedule="launches")
+    got = _run(g, Q, s, 50, **best)
+    for u, v in zip(ref, got):
+        assert np.array_equal(u, v)
