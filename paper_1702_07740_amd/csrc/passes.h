@@ -390,6 +390,50 @@ __device__ __forceinline__ FixedRow<D, DS, Msg> fixed_row(const CodeDev &c, cons
     return R;
 }
 
+// Step 2 of one check of degree D whose first DS inputs are stored edges and
+// the others degree-1 inputs (Psi, already in the Phi domain).  From the
+// inputs x (L_vc, or Psi): the input signs neg, the Phi values ph and the
+// exclusive Phi sums ex, as prefix sums from the left plus suffix sums from
+// the right (a fixed order).  Returns the check's sign parity, the syndrome
+// bit included: the message to input k is negative iff parity ^ neg[k].
+template <int D, int DS>
+__device__ __forceinline__ bool phi_exclusive(const float (&x)[D], bool syn, const PhiConsts &PK,
+                                              bool (&neg)[D], float (&ph)[D], float (&ex)[D]) {
+    bool par = syn;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        neg[k] = x[k] < 0.0f;
+        par ^= neg[k];
+        ph[k] = (k < DS) ? phi2(fabsf(x[k]), PK) : fabsf(x[k]);
+    }
+    if constexpr (D == 1) {
+        ex[0] = 0.0f;
+    } else {
+        float pre[D];
+        pre[0] = 0.0f;
+#pragma unroll
+        for (int k = 1; k < D; ++k) pre[k] = (k == 1) ? ph[0] : pre[k - 1] + ph[k - 1];
+        float suf = ph[D - 1];
+        ex[D - 1] = pre[D - 1];
+#pragma unroll
+        for (int k = D - 2; k >= 0; --k) {
+            ex[k] = (k == 0) ? suf : pre[k] + suf;
+            suf += ph[k];
+        }
+    }
+    return par;
+}
+
+// Decision of a degree-1 variable: the sign of Q + m, taken in the Phi domain
+// (|Q| > |m| exactly when Phi(|Q|) < S, S the exclusive sum of the check's
+// other inputs).  The signs of Q and m differ exactly when the check's whole
+// sign parity is odd; then the larger magnitude decides.
+__device__ __forceinline__ bool d1_decision(bool neg, bool par, float ph, float ex,
+                                            const PhiConsts &PK) {
+    const float S = __builtin_amdgcn_fmed3f(ex, kPhiLo, PK.hi);
+    return neg ^ (par && !(ph < S));
+}
+
 // K checks a + 256 q (q < K) of a fixed row; w = the wave's word of check a.
 // Padding lanes (check >= Z) read in-bounds slack (the row stride of the
 // totals and the padding after the message and Psi regions cover them), are
@@ -454,31 +498,9 @@ __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const
         const unsigned aq = a + q * kBlock;
         const bool valid = aq < R.Z;
         // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
-        float ph[D];
+        float ph[D], ex[D];
         bool neg[D];
-        bool par = lane_bit(sw[q]);
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            neg[k] = x[q][k] < 0.0f;
-            par ^= neg[k];
-            ph[k] = (k < DS) ? phi2(fabsf(x[q][k]), PK) : fabsf(x[q][k]);
-        }
-        float ex[D];
-        if constexpr (D == 1) {
-            ex[0] = 0.0f;
-        } else {
-            float pre[D];
-            pre[0] = 0.0f;
-#pragma unroll
-            for (int k = 1; k < D; ++k) pre[k] = (k == 1) ? ph[0] : pre[k - 1] + ph[k - 1];
-            float suf = ph[D - 1];
-            ex[D - 1] = pre[D - 1];
-#pragma unroll
-            for (int k = D - 2; k >= 0; --k) {
-                ex[k] = (k == 0) ? suf : pre[k] + suf;
-                suf += ph[k];
-            }
-        }
+        const bool par = phi_exclusive<D, DS>(x[q], lane_bit(sw[q]), PK, neg, ph, ex);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const bool sgn = par ^ neg[k];  // the message to block k is negative
@@ -486,12 +508,7 @@ __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const
                 const float mag = phi2(ex[k], PK);
                 if (valid) msg_store<Msg>(&at(R.msg[k] + q * kBlock, a), sgn ? -mag : mag);
             } else {
-                // decision of the degree-1 variable: sign of Q + m, decided in
-                // the Phi domain (|Q| > |m| exactly when Phi(|Q|) < S).  The
-                // signs of Q and m differ exactly when the check's whole sign
-                // parity `par` is odd; then the larger magnitude decides.
-                const float S = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, PK.hi);
-                const bool d = neg[k] ^ (par && !(ph[k] < S));
+                const bool d = d1_decision(neg[k], par, ph[k], ex[k], PK);
                 const unsigned long long bits = wave_ballot(valid && d);
                 if ((threadIdx.x & 63) == 0 && valid) at(R.dcur[k], w + 4u * q) = bits;
                 if constexpr (with_post(MODE)) {

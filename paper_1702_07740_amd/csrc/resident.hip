@@ -53,27 +53,6 @@ __device__ __forceinline__ bool res_stored(int k, int ns) {
     else return k < ns;
 }
 
-// Exclusive Phi sums of a check's inputs, in the order of the per-iteration
-// decoder: prefix sums from the left, suffix sums from the right.
-template <int D>
-__device__ __forceinline__ void res_exclusive(const float (&ph)[D], float (&ex)[D]) {
-    if constexpr (D == 1) {
-        ex[0] = 0.0f;
-    } else {
-        float pre[D];
-        pre[0] = 0.0f;
-#pragma unroll
-        for (int k = 1; k < D; ++k) pre[k] = (k == 1) ? ph[0] : pre[k - 1] + ph[k - 1];
-        float suf = ph[D - 1];
-        ex[D - 1] = pre[D - 1];
-#pragma unroll
-        for (int k = D - 2; k >= 0; --k) {
-            ex[k] = (k == 0) ? suf : pre[k] + suf;
-            suf += ph[k];
-        }
-    }
-}
-
 // K units of a common row class (degree D, DS stored blocks, then one
 // degree-1 block if DS < D): for each q < K, checks ch[q]*64 + lane of the
 // row whose resident descriptor is d[q].  The K units' loads issue together,
@@ -131,14 +110,7 @@ __device__ __forceinline__ bool res_fixed(const ResView<Msg> &S, const int32_t *
         // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
         float ph[D], ex[D];
         bool neg[D];
-        bool p2 = (sw[q] >> lane) & 1ull;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            neg[k] = x[q][k] < 0.0f;
-            p2 ^= neg[k];
-            ph[k] = (k < DS) ? phi2(fabsf(x[q][k]), PK) : fabsf(x[q][k]);
-        }
-        res_exclusive<D>(ph, ex);
+        const bool p2 = phi_exclusive<D, DS>(x[q], (sw[q] >> lane) & 1ull, PK, neg, ph, ex);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const bool sgn = p2 ^ neg[k];  // the message to block k is negative
@@ -146,9 +118,7 @@ __device__ __forceinline__ bool res_fixed(const ResView<Msg> &S, const int32_t *
                 const float mag = phi2(ex[k], PK);
                 if (valid[q]) msg_store<Msg>(&S.msg[idx[q][k]], sgn ? -mag : mag);
             } else {
-                // degree-1 decision, sign of Q + m, taken in the Phi domain
-                const float Sx = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, PK.hi);
-                const bool dd = neg[k] ^ (p2 && !(ph[k] < Sx));
+                const bool dd = d1_decision(neg[k], p2, ph[k], ex[k], PK);
                 const unsigned long long bits = wave_ballot(valid[q] && dd);
                 if (lane == 0) dcur[idx[q][k]] = bits;
             }
@@ -238,8 +208,7 @@ __device__ __forceinline__ bool res_generic(const CodeDev &c, const ResView<Msg>
             const float mag = phi2(ex[k], PK);
             if (valid) msg_store<Msg>(&S.msg[idx[k]], sgn ? -mag : mag);
         } else {
-            const float Sx = __builtin_amdgcn_fmed3f(ex[k], kPhiLo, PK.hi);
-            const bool dd = neg[k] ^ (p2 && !(ph[k] < Sx));
+            const bool dd = d1_decision(neg[k], p2, ph[k], ex[k], PK);
             const unsigned long long bits = wave_ballot(valid && dd);
             if (lane == 0) dcur[idx[k]] = bits;
         }
