@@ -45,14 +45,6 @@ struct ResView {
     unsigned Z, W, Zp;
 };
 
-// Block k of a row is a stored block: DS >= 0 is a compile-time split, DS < 0
-// reads the row's count.
-template <int DS>
-__device__ __forceinline__ bool res_stored(int k, int ns) {
-    if constexpr (DS >= 0) return k < DS;
-    else return k < ns;
-}
-
 // K units of a common row class (degree D, DS stored blocks, then one
 // degree-1 block if DS < D): for each q < K, checks ch[q]*64 + lane of the
 // row whose resident descriptor is d[q].  The K units' loads issue together,
