@@ -274,10 +274,11 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         }
     }
     const size_t o_resd = put(res_desc);
-    // rows padded to whole batches of 8 pairs, plus one batch of slack, so a
-    // batch read from any in-range start stays inside the table
-    const int res_stride = (tab_stride + 15) / 16 * 16;
-    std::vector<int32_t> res_core((size_t)std::max(NC, 1) * res_stride + 16, 0);
+    // rows padded to whole batches of kResVnBatch pairs, plus one batch of
+    // slack, so a batch read from any in-range start stays inside the table
+    const int res_batch = 2 * ldpc::kResVnBatch;
+    const int res_stride = (tab_stride + res_batch - 1) / res_batch * res_batch;
+    std::vector<int32_t> res_core((size_t)std::max(NC, 1) * res_stride + res_batch, 0);
     for (int k = 0; k < NC; ++k)
         for (int i = 0; i < core_deg[k]; ++i) {
             res_core[(size_t)k * res_stride + 2 * i] = core_state[core_first[k] + i] * Z;

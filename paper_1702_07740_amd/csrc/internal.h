@@ -33,8 +33,9 @@ constexpr int kFixedClasses = 2 * kSmallRowDegree;
 constexpr int kRowDescWords = 20;
 
 // Words of a row's descriptor for the frame-resident schedule (see
-// CodeDev::res_desc).
+// CodeDev::res_desc), and the blocks its variable phase reads per batch.
 constexpr int kResDescWords = 24;
+constexpr int kResVnBatch = 16;
 
 // Default and largest checks per thread of the common-row check kernel.
 constexpr int kDefaultChecksPerThread = 4;
@@ -103,7 +104,8 @@ struct CodeDev {
     //   [17, 23) shift of block k
     // and per core column k, at res_core[k * res_core_stride], its blocks as
     // (state index * Z, shift) pairs in increasing row order (rows padded with
-    // zero pairs to a multiple of 8 pairs, and 8 more pairs after the last)
+    // zero pairs to a multiple of kResVnBatch pairs, and kResVnBatch more
+    // pairs after the last)
     const int32_t *res_desc, *res_core;
     int32_t res_core_stride;
     // the check-phase units (base row r, chunk ch of 64 checks) as r | ch << 16,
@@ -153,7 +155,7 @@ hipError_t enqueue_decode(const DecodeLaunch &l);
 // Frame-resident schedule (resident.hip): one workgroup per frame runs every
 // iteration with the frame's state in LDS.  Byte offsets of that state:
 struct ResidentLayout {
-    size_t tot, syn, d1, flag, total;  // messages at 0; total = LDS bytes per workgroup
+    size_t tot, q, part, syn, d1, flag, total;  // messages at 0; total = LDS bytes per workgroup
 };
 ResidentLayout resident_layout(const CodeDev &c, bool fp16);
 
@@ -166,7 +168,7 @@ struct ResidentArgs {
     uint8_t *conv_out;
     size_t psi_frame;
     int T, early_stop, check_from;
-    unsigned lds_tot, lds_syn, lds_d1, lds_flag;
+    unsigned lds_tot, lds_q, lds_part, lds_syn, lds_d1, lds_flag;
 };
 
 // Enqueue a whole decode as one resident launch (no posteriors, no per-pass

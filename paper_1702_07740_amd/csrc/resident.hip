@@ -8,8 +8,9 @@
 // frame's check-to-variable messages, core totals, packed syndrome and
 // degree-1 decision bits live in LDS (160 KB per CU), the iteration loop runs
 // inside the kernel, and the only synchronisation is the workgroup barrier
-// between the check phase (Alg. 1 Step 2, with the Step 4 check of the
-// previous iteration) and the variable phase (Step 3).  Global memory is
+// between the phases of an iteration: the check phase (Alg. 1 Step 2, with
+// the Step 4 check of the previous iteration), the row-group sums of the
+// variable phase (Step 3), and the core totals.  Global memory is
 // touched only to read the channel LLRs, to hold the degree-1 inputs Psi
 // (read-only after the first phase), and to write the outputs.
 //
@@ -34,12 +35,12 @@ namespace {
 using namespace dev;
 
 constexpr int kResThreads = 1024;  // 16 wave64s: four per SIMD of the one CU
-constexpr int kResVnBatch = 8;     // variable phase: blocks loaded together
 
 template <typename Msg>
 struct ResView {
     Msg *msg;            // [NS][Z] messages, check order (LDS)
     float *tot;          // [NC][Z] core totals, base 2 (LDS)
+    const float *q;      // [NC][Z] channel LLRs of the core variables (LDS)
     const uint64_t *syn; // [mb][W] packed syndrome bits (LDS)
     const float *psi;    // [ND1][Zp] +-Phi(|Q|) of the degree-1 variables, check order (global)
     unsigned Z, W, Zp;
@@ -265,46 +266,57 @@ __device__ __forceinline__ bool res_check_phase(const CodeDev &c, const ResView<
     return bad;
 }
 
-// Variable phase: L_v = Q_v log2(e) + S0 + S1 per core variable, S0 and S1
-// the sums of the column's first ceil(deg / 2) and remaining blocks, each in
-// increasing row order (the per-iteration decoder's two row groups).
+// Variable phase, first half: the row-group sums S0 and S1 of every core
+// variable (the column's first ceil(deg / 2) blocks and the rest, each summed
+// in increasing row order, as in the per-iteration decoder), one wave per
+// (column, 64 variables, group), into part[g].
 template <typename Msg>
-__device__ __forceinline__ void res_variable_phase(const CodeDev &c, const ResView<Msg> &S,
-                                                   const float *llr) {
+__device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<Msg> &S,
+                                               float *const (&part)[kVnGroups]) {
     const unsigned nw = blockDim.x >> 6;
     const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const unsigned Z = S.Z, units = (unsigned)c.NC * S.W;
+    const unsigned Z = S.Z, units = (unsigned)c.NC * S.W * kVnGroups;
     for (unsigned u = wave; u < units; u += nw) {
-        const int k = (int)(u / S.W);
-        const unsigned j = (u - (unsigned)k * S.W) * 64u + (threadIdx.x & 63u);
+        const int g = (int)(u % kVnGroups);
+        const unsigned kc = u / kVnGroups;
+        const int k = (int)(kc / S.W);
+        const unsigned j = (kc - (unsigned)k * S.W) * 64u + (threadIdx.x & 63u);
         if (j >= Z) continue;
         const int deg = uniform_i32(c.core_deg + k);
         const int per = (deg + kVnGroups - 1) / kVnGroups;
         const int32_t *tab = c.res_core + (size_t)k * c.res_core_stride;
-        const float q = llr[(size_t)uniform_i32(c.core_col + k) * Z + j];
         // batches of kResVnBatch blocks: one burst of table loads, then their
         // LDS loads together.  Entries past the group's end (the next group's,
         // or zero padding: valid offsets either way) add +0, which leaves a
         // sum that started at +0 unchanged.
-        float p[kVnGroups];
+        float p = 0.0f;
+        const int e = min(deg, (g + 1) * per);
+        for (int i0 = g * per; i0 < e; i0 += kResVnBatch) {
+            float xv[kResVnBatch];
 #pragma unroll
-        for (int g = 0; g < kVnGroups; ++g) {
-            p[g] = 0.0f;
-            const int e = min(deg, (g + 1) * per);
-            for (int i0 = g * per; i0 < e; i0 += kResVnBatch) {
-                float xv[kResVnBatch];
-#pragma unroll
-                for (int u2 = 0; u2 < kResVnBatch; ++u2) {
-                    const unsigned off = (unsigned)uniform_i32(tab + 2 * (i0 + u2));
-                    const unsigned s = (unsigned)uniform_i32(tab + 2 * (i0 + u2) + 1);
-                    const unsigned idx = (j >= s) ? j - s : j + Z - s;
-                    xv[u2] = msg_load<Msg>(&S.msg[off + idx]);
-                }
-#pragma unroll
-                for (int u2 = 0; u2 < kResVnBatch; ++u2) p[g] += (i0 + u2 < e) ? xv[u2] : 0.0f;
+            for (int u2 = 0; u2 < kResVnBatch; ++u2) {
+                const unsigned off = (unsigned)uniform_i32(tab + 2 * (i0 + u2));
+                const unsigned s = (unsigned)uniform_i32(tab + 2 * (i0 + u2) + 1);
+                const unsigned idx = (j >= s) ? j - s : j + Z - s;
+                xv[u2] = msg_load<Msg>(&S.msg[off + idx]);
             }
+#pragma unroll
+            for (int u2 = 0; u2 < kResVnBatch; ++u2) p += (i0 + u2 < e) ? xv[u2] : 0.0f;
         }
-        S.tot[(unsigned)k * Z + j] = core_total(q, p);
+        part[g][(unsigned)k * Z + j] = p;
+    }
+}
+
+// Variable phase, second half (after a barrier): L_v = (Q_v log2(e) + S0) + S1.
+template <typename Msg>
+__device__ __forceinline__ void res_totals(const CodeDev &c, const ResView<Msg> &S,
+                                           float *const (&part)[kVnGroups]) {
+    const unsigned n = (unsigned)c.NC * S.Z;
+    for (unsigned i = threadIdx.x; i < n; i += blockDim.x) {
+        float ps[kVnGroups];
+#pragma unroll
+        for (int g = 0; g < kVnGroups; ++g) ps[g] = part[g][i];
+        S.tot[i] = core_total(S.q[i], ps);
     }
 }
 
@@ -316,6 +328,10 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     ResView<Msg> S;
     S.msg = reinterpret_cast<Msg *>(lds);
     S.tot = reinterpret_cast<float *>(lds + A.lds_tot);
+    float *qc = reinterpret_cast<float *>(lds + A.lds_q);
+    S.q = qc;
+    float *const part[kVnGroups] = {reinterpret_cast<float *>(lds + A.lds_part),
+                                    reinterpret_cast<float *>(lds + A.lds_part) + c.NC * c.Z};
     uint64_t *syn = reinterpret_cast<uint64_t *>(lds + A.lds_syn);
     S.syn = syn;
     uint64_t *d1 = reinterpret_cast<uint64_t *>(lds + A.lds_d1);  // [2][ND1][W]
@@ -332,12 +348,15 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const PhiConsts PK = phi_consts();
 
-    // Set-up: zero messages, totals of iteration 0, Psi and the channel-sign
-    // decision bits of the degree-1 variables, packed syndrome, vote flags.
+    // Set-up: zero messages, the core LLRs and the totals of iteration 0, Psi
+    // and the channel-sign decision bits of the degree-1 variables, packed
+    // syndrome, vote flags.
     for (unsigned i = threadIdx.x; i < (unsigned)c.NS * Z; i += nt) msg_store<Msg>(&S.msg[i], 0.0f);
     for (unsigned i = threadIdx.x; i < (unsigned)c.NC * Z; i += nt) {
         const unsigned k = i / Z, j = i - k * Z;
-        S.tot[i] = llr[(size_t)c.core_col[k] * Z + j] * kLog2e;
+        const float q = llr[(size_t)c.core_col[k] * Z + j];
+        qc[i] = q;
+        S.tot[i] = q * kLog2e;
     }
     for (unsigned u = wave; u < (unsigned)c.ND1 * W; u += nw) {
         const unsigned k = u / W, a = (u - k * W) * 64u + lane;
@@ -381,7 +400,9 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
         }
         // flag[(t + 1) & 1] was last read before the previous barrier
         if (threadIdx.x == 0) flag[(t + 1) & 1] = 0;
-        res_variable_phase<Msg>(c, S, llr);
+        res_group_sums<Msg>(c, S, part);
+        __syncthreads();
+        res_totals<Msg>(c, S, part);
         __syncthreads();
     }
     if (!stopped) {
@@ -421,7 +442,9 @@ ResidentLayout resident_layout(const CodeDev &c, bool fp16) {
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
     ResidentLayout L{};
     L.tot = a16((size_t)c.NS * c.Z * (fp16 ? 2 : 4));
-    L.syn = a16(L.tot + (size_t)c.NC * c.Z * 4);
+    L.q = a16(L.tot + (size_t)c.NC * c.Z * 4);
+    L.part = a16(L.q + (size_t)c.NC * c.Z * 4);
+    L.syn = a16(L.part + (size_t)kVnGroups * c.NC * c.Z * 4);
     L.d1 = L.syn + (size_t)c.mb * c.W * 8;
     L.flag = L.d1 + 2 * (size_t)c.ND1 * c.W * 8;
     L.total = a16(L.flag + 2 * 4);
@@ -444,6 +467,8 @@ hipError_t enqueue_resident(const DecodeLaunch &l, const WorkLayout &W, size_t l
     a.early_stop = l.early_stop;
     a.check_from = l.check_from;
     a.lds_tot = (unsigned)R.tot;
+    a.lds_q = (unsigned)R.q;
+    a.lds_part = (unsigned)R.part;
     a.lds_syn = (unsigned)R.syn;
     a.lds_d1 = (unsigned)R.d1;
     a.lds_flag = (unsigned)R.flag;
