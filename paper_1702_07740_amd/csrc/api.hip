@@ -417,7 +417,7 @@ namespace {
 // launches take kLaunchFixedNs plus kLaunchWgNs per workgroup of the two
 // passes (256-thread check tiles of 256 * cpt checks, variable tiles of 128
 // or, with half messages, 256 variables).
-constexpr double kResidentUnitNs = 85.0;
+constexpr double kResidentUnitNs = 80.0;
 constexpr int kResidentFramesPerRound = 256;
 constexpr double kLaunchFixedNs = 7000.0;
 constexpr double kLaunchWgNs = 2.35;
