@@ -213,3 +213,22 @@ def test_autotuner_picks_the_fastest_schedule(ldpc, oracle_mod, tmp_path, monkey
     got = _run(g, Q, s, 50, **best)
     for u, v in zip(ref, got):
         assert np.array_equal(u, v)
+
+
+def test_lds_budget_boundary(ldpc, oracle_mod):
+    """At Z = 128 the R = 0.02 template's FP32 state (306 blocks x 128 x 4 B =
+    157 KB of messages alone) exceeds one workgroup's LDS, while its FP16
+    state fits: the resident schedule is refused for FP32 and runs, bit-exact
+    against the launches, for FP16 messages."""
+    Z, F = 128, 8
+    base = synth.template_base(144, Z, seed=1)
+    g, o = ldpc.Code(base, Z), oracle_mod.OracleCode(base, Z)
+    assert g.schedule(F=1024) == "launches"
+    with pytest.raises(ldpc.LdpcError) as e:
+        g.schedule(F=1, schedule="resident")
+    assert e.value.status == ldpc.LDPC_EUNSUPPORTED
+    assert g.schedule(F=1, msg_fp16=True, schedule="resident") == "resident"
+    x, Q = synth.biawgn_frames(o.n, F, -13.8, seed=128)
+    s = o.syndrome(x)
+    _say("LDS budget boundary", Z, F)
+    _same(g, Q, s, 100, msg_fp16=True)
