@@ -209,8 +209,9 @@ __device__ __forceinline__ bool res_generic(const CodeDev &c, const ResView<Msg>
     return bad;
 }
 
-// One unit (row descriptor d, chunk ch) of any class.
-template <bool UPDATE, typename Msg>
+// One unit (row descriptor d, chunk ch) of any class (GENERIC = false: the
+// code has common rows only).
+template <bool UPDATE, typename Msg, bool GENERIC>
 __device__ __forceinline__ bool res_unit(const CodeDev &c, const ResView<Msg> &S, int cls,
                                          const int32_t *d, unsigned ch, const uint64_t *dprev,
                                          uint64_t *dcur, const PhiConsts &PK) {
@@ -222,17 +223,20 @@ __device__ __forceinline__ bool res_unit(const CodeDev &c, const ResView<Msg> &S
         LDPC_RES(0, 1, 0) LDPC_RES(1, 1, 1) LDPC_RES(2, 2, 1) LDPC_RES(3, 2, 2)
         LDPC_RES(4, 3, 2) LDPC_RES(5, 3, 3) LDPC_RES(6, 4, 3) LDPC_RES(7, 4, 4)
         LDPC_RES(8, 5, 4) LDPC_RES(9, 5, 5) LDPC_RES(10, 6, 5) LDPC_RES(11, 6, 6)
-        case 12: return res_generic<8, UPDATE, Msg>(c, S, d, ch, dprev, dcur, PK);
-        case 13: return res_generic<16, UPDATE, Msg>(c, S, d, ch, dprev, dcur, PK);
-        default: return false;
+        default: break;
     }
 #undef LDPC_RES
+    if constexpr (GENERIC) {
+        if (cls == 12) return res_generic<8, UPDATE, Msg>(c, S, d, ch, dprev, dcur, PK);
+        if (cls == 13) return res_generic<16, UPDATE, Msg>(c, S, d, ch, dprev, dcur, PK);
+    }
+    return false;
 }
 
 // Check phase of one frame.  The units (row, chunk of 64 checks) are listed
 // with the rows in class order; the waves take pairs of consecutive units in
 // turn, and a pair of one common class runs as one two-unit chain.
-template <bool UPDATE, typename Msg>
+template <bool UPDATE, typename Msg, bool GENERIC>
 __device__ __forceinline__ bool res_check_phase(const CodeDev &c, const ResView<Msg> &S,
                                                 const uint64_t *dprev, uint64_t *dcur,
                                                 const PhiConsts &PK) {
@@ -259,8 +263,9 @@ __device__ __forceinline__ bool res_check_phase(const CodeDev &c, const ResView<
             }
 #undef LDPC_RES2
         } else {
-            bad |= res_unit<UPDATE, Msg>(c, S, cls0, d[0], ch[0], dprev, dcur, PK);
-            if (two) bad |= res_unit<UPDATE, Msg>(c, S, cls1, d[1], ch[1], dprev, dcur, PK);
+            bad |= res_unit<UPDATE, Msg, GENERIC>(c, S, cls0, d[0], ch[0], dprev, dcur, PK);
+            if (two)
+                bad |= res_unit<UPDATE, Msg, GENERIC>(c, S, cls1, d[1], ch[1], dprev, dcur, PK);
         }
     }
     return bad;
@@ -320,7 +325,10 @@ __device__ __forceinline__ void res_totals(const CodeDev &c, const ResView<Msg> 
     }
 }
 
-template <typename Msg>
+// kGeneric: the code has rows outside the common classes (degree > 6, or more
+// than one degree-1 block).  Their code path holds many more registers, so
+// codes without such rows run an instantiation that leaves it out.
+template <typename Msg, bool kGeneric>
 __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, ResidentArgs A) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int f = blockIdx.x;
@@ -387,7 +395,7 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     bool stopped = false;
     for (int t = 1; t <= T; ++t) {
         const bool vote = checked(t - 1);
-        const bool bad = res_check_phase<true, Msg>(c, S, d1 + ((t - 1) & 1) * d1n,
+        const bool bad = res_check_phase<true, Msg, kGeneric>(c, S, d1 + ((t - 1) & 1) * d1n,
                                                     d1 + (t & 1) * d1n, PK);
         if (vote && wave_ballot(bad) != 0ull && lane == 0) flag[t & 1] = 1;
         __syncthreads();
@@ -407,7 +415,8 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     }
     if (!stopped) {
         // the check of the last iteration (the channel decisions when T = 0)
-        const bool bad = res_check_phase<false, Msg>(c, S, d1 + (T & 1) * d1n, nullptr, PK);
+        const bool bad =
+            res_check_phase<false, Msg, kGeneric>(c, S, d1 + (T & 1) * d1n, nullptr, PK);
         if (wave_ballot(bad) != 0ull && lane == 0) flag[(T + 1) & 1] = 1;
         __syncthreads();
         conv = flag[(T + 1) & 1] == 0;
@@ -473,18 +482,18 @@ hipError_t enqueue_resident(const DecodeLaunch &l, const WorkLayout &W, size_t l
     a.lds_d1 = (unsigned)R.d1;
     a.lds_flag = (unsigned)R.flag;
     const dim3 grid((unsigned)l.F), block(kResThreads);
-    if (l.fp16) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(resident_decode<_Float16>),
+    auto launch = [&](auto kernel) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)R.total);
         if (e != hipSuccess) return e;
-        resident_decode<_Float16><<<grid, block, R.total, l.stream>>>(c, a);
-    } else {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(resident_decode<float>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)R.total);
-        if (e != hipSuccess) return e;
-        resident_decode<float><<<grid, block, R.total, l.stream>>>(c, a);
-    }
-    return hipGetLastError();
+        kernel<<<grid, block, R.total, l.stream>>>(c, a);
+        return hipGetLastError();
+    };
+    const bool generic = c.n_large > 0;
+    if (l.fp16)
+        return generic ? launch(resident_decode<_Float16, true>)
+                       : launch(resident_decode<_Float16, false>);
+    return generic ? launch(resident_decode<float, true>) : launch(resident_decode<float, false>);
 }
 
 }  // namespace ldpc
