@@ -125,7 +125,7 @@ typedef struct {
  *            LDS: for small liftings, where the per-iteration launches are
  *            latency-bound.  Needs llr_out and timing_events unset and the
  *            frame's state within one workgroup's LDS (160 KB on MI355X:
- *            state edges * (4 or 2 bytes) + core variables * 4 + bit arrays).
+ *            state edges * (4 or 2 bytes) + core variables * 16 + bit arrays).
  *  AUTO      RESIDENT when it is possible and a cost model of both, fitted
  *            to measurements, favours it (many frames of a small code), else
  *            LAUNCHES.
