@@ -99,7 +99,8 @@ typedef struct {
     int32_t msg_fp16;        /* 1: check-to-variable messages stored as IEEE half;
                                 all arithmetic and sums stay in float32             */
     int32_t checks_per_thread; /* schedule of the check kernel: checks of one base
-                                row per thread, 1, 2 or 4 (0 = library default 4);
+                                row per thread, 1, 2 or 4 (0 = library default:
+                                1 for Z <= 256, else 4);
                                 a block row's Z checks take ceil(Z / (256 *
                                 checks_per_thread)) workgroups.  Results do not
                                 depend on it                                      */
