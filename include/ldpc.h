@@ -233,7 +233,10 @@ int ldpc_reconciliation_message(int32_t d, int32_t F, int32_t n, const uint8_t *
  *
  * The engine owns its device memory: a cap of hbm_budget_bytes on the state of
  * admitted requests, taken from the device in chunks of up to 1 GiB when first
- * needed and kept until ldpc_engine_destroy.  Calls on one engine must not run
+ * needed.  The chunks together never exceed hbm_budget_bytes: a request that
+ * fits the budget but no free range waits in the queue, and chunks with
+ * nothing in flight are returned to the device when a request needs the room;
+ * the rest are kept until ldpc_engine_destroy.  Calls on one engine must not run
  * concurrently.  Supported codes: every base row of degree <= 6 with at most one
  * degree-1 block (the multi-edge families); others give LDPC_EUNSUPPORTED.
  */

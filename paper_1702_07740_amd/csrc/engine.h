@@ -39,7 +39,10 @@ struct Request {
 };
 
 // Device memory in 1 GiB chunks (or the budget if smaller), allocated on
-// first need and kept until the engine is destroyed; first-fit sub-allocation.
+// first need; first-fit sub-allocation.  The chunks together never exceed
+// the engine's budget: a request that fits the budget but no free range
+// waits, and chunks left entirely free are returned to the device when a
+// larger request needs the room.
 struct Arena {
     struct Range {
         size_t off, size;
@@ -50,10 +53,12 @@ struct Arena {
         std::vector<Range> free_list;  // sorted by offset
     };
     size_t chunk_bytes = 0;
+    size_t total_bytes = 0;  // device bytes held in chunks
     std::vector<Chunk> chunks;
     void *alloc(size_t bytes);
-    bool grow(size_t at_least);
+    bool grow(size_t at_least, size_t cap);
     void release(void *p, size_t bytes);
+    void free_idle_chunks(hipStream_t stream);
     void destroy();
 };
 

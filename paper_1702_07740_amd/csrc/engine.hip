@@ -242,12 +242,36 @@ void *Arena::alloc(size_t bytes) {
     return nullptr;
 }
 
-bool Arena::grow(size_t at_least) {
-    const size_t size = std::max(chunk_bytes, round_up(at_least, 256));
+// A new chunk of at least `at_least` bytes, if the chunks stay within `cap`.
+bool Arena::grow(size_t at_least, size_t cap) {
+    size_t size = std::max(chunk_bytes, round_up(at_least, 256));
+    if (total_bytes + size > cap) size = round_up(at_least, 256);  // a last, smaller chunk
+    if (total_bytes + size > cap) return false;
     void *p = nullptr;
     if (hipMalloc(&p, size) != hipSuccess) return false;
     chunks.push_back(Chunk{p, size, {Range{0, size}}});
+    total_bytes += size;
     return true;
+}
+
+// Return every chunk with no live allocation to the device, after the work
+// enqueued on `stream` (read-outs of retired requests) has finished with it.
+void Arena::free_idle_chunks(hipStream_t stream) {
+    bool synced = false;
+    for (size_t i = 0; i < chunks.size();) {
+        Chunk &ch = chunks[i];
+        if (ch.free_list.size() == 1 && ch.free_list[0].off == 0 && ch.free_list[0].size == ch.size) {
+            if (!synced) {
+                (void)hipStreamSynchronize(stream);
+                synced = true;
+            }
+            (void)hipFree(ch.base);
+            total_bytes -= ch.size;
+            chunks.erase(chunks.begin() + (long)i);
+        } else {
+            ++i;
+        }
+    }
 }
 
 void Arena::release(void *p, size_t bytes) {
@@ -275,6 +299,7 @@ void Arena::release(void *p, size_t bytes) {
 void Arena::destroy() {
     for (Chunk &ch : chunks) (void)hipFree(ch.base);
     chunks.clear();
+    total_bytes = 0;
 }
 
 // ------------------------------------------------------------------ engine
@@ -337,8 +362,14 @@ bool Engine::admit_one(const Request &rq, int s) {
     if (in_use + need > budget_bytes) return false;
     void *p = arena.alloc(need);
     if (!p) {
-        if (!arena.grow(need)) return false;
-        p = arena.alloc(need);
+        // the chunks may not outgrow the budget: first return idle chunks
+        // (which only frees room when nothing of theirs is in flight)
+        if (!arena.grow(need, budget_bytes)) {
+            arena.free_idle_chunks(stream);
+            p = arena.alloc(need);
+            if (!p && !arena.grow(need, budget_bytes)) return false;
+        }
+        if (!p) p = arena.alloc(need);
         if (!p) return false;
     }
     in_use += need;

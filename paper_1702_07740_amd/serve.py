@@ -55,6 +55,13 @@ class Req:
     done_at: float = field(default=float("nan"))
 
 
+def pool_frames(rate, Z, n, frames_per_pool=8, seed=5):
+    """Host inputs (key bits, channel LLRs) of the (rate, Z) pool: frames at the
+    code's BP threshold + THRESHOLD_MARGIN_DB, drawn from a seed of their own."""
+    snr = template_thresholds()[rate] + THRESHOLD_MARGIN_DB
+    return synth.biawgn_frames(n, frames_per_pool, snr, seed=seed + 1000 * Z + int(rate * 1000))
+
+
 def make_pools(ldpc, torch, lifts=LIFTS, rates=RATES, frames_per_pool=8, seed=5):
     thr = template_thresholds()
     pools = []
@@ -63,7 +70,7 @@ def make_pools(ldpc, torch, lifts=LIFTS, rates=RATES, frames_per_pool=8, seed=5)
             base = synth.template_for_rate(rate, Z, seed=1)
             code = ldpc.Code(base, Z)
             snr = thr[rate] + THRESHOLD_MARGIN_DB
-            x, Q = synth.biawgn_frames(code.n, frames_per_pool, snr, seed=seed + 1000 * Z + int(rate * 1000))
+            x, Q = pool_frames(rate, Z, code.n, frames_per_pool, seed)
             dQ = torch.from_numpy(Q).cuda()
             syn = code.syndrome(torch.from_numpy(x).cuda())
             pools.append(Pool(rate, Z, code, dQ, syn, snr))

@@ -1,9 +1,11 @@
 """Multi-request engine: every request's outputs equal ldpc_decode_batch on the
-same inputs, bit for bit, whatever else is in flight."""
+same inputs, bit for bit, whatever else is in flight, and meet the FP64
+oracle's parity contract (Alg. 1, Sec. III-D) on their own."""
 import numpy as np
 import pytest
 
 from paper_1702_07740_amd import synth
+from tests.parity import check_decode_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -28,10 +30,13 @@ def _dev(a):
 
 
 def _requests(ldpc, oracle_mod, seed):
-    """Requests of mixed rate, lifting size and frame count, in the waterfall."""
+    """Requests of mixed rate, lifting size and frame count, in the waterfall.
+
+    Returns (code, Q, s, T, oracle code, host Q, host s) per request; the
+    syndromes come from the oracle."""
     specs = [(0.02, 64, 3, -14.0), (0.05, 100, 2, -10.2), (0.1, 63, 4, -6.8),
              (0.02, 128, 1, -13.8), (0.1, 200, 2, -7.0), (0.05, 64, 4, -10.0),
-             (0.02, 64, 2, -15.4), (0.1, 63, 1, -6.5)]
+             (0.02, 64, 2, -15.4), (0.1, 63, 1, -6.5), (0.05, 2048, 2, -10.3)]
     out = []
     for i, (rate, Z, F, snr) in enumerate(specs):
         base = synth.template_for_rate(rate, Z, seed=1)
@@ -39,8 +44,16 @@ def _requests(ldpc, oracle_mod, seed):
         o = oracle_mod.OracleCode(base, Z)
         x, Q = synth.biawgn_frames(o.n, F, snr, seed=seed * 100 + i)
         s = o.syndrome(x)
-        out.append((g, _dev(Q), _dev(s), 60 if i % 3 else 40))
+        out.append((g, _dev(Q), _dev(s), 60 if i % 3 else 40, o, Q, s))
     return out
+
+
+def _oracle_parity(req, outs, fp16=False):
+    """The engine's outputs of one request against the oracle's decode."""
+    g, dQ, ds, T, o, Q, s = req
+    bits, it, conv = (np.asarray(u.cpu().numpy() if hasattr(u, "cpu") else u) for u in outs)
+    ref = o.decode(Q, s, T, threads=4)
+    return check_decode_parity(o, Q, s, bits, it, conv, ref, T, fp16=fp16)
 
 
 def _alone(g, Q, s, T, fp16):
@@ -56,16 +69,19 @@ def test_engine_results_equal_decode_batch(ldpc, oracle_mod, fp16):
     _say("engine vs alone", "fp16" if fp16 else "fp32")
     tickets = []
     # staggered arrivals: some now, the rest while the first ones decode
-    for i, (g, Q, s, T) in enumerate(reqs):
+    for i, (g, Q, s, T, *_) in enumerate(reqs):
         tickets.append(eng.submit(g, Q, s, T))
         if i % 2 == 1:
             for _ in range(7):
                 eng.step()
     res = eng.drain(tickets)
-    for (g, Q, s, T), t in zip(reqs, tickets):
+    for req, t in zip(reqs, tickets):
+        g, Q, s, T = req[:4]
         bits, it, conv = (r.cpu().numpy() for r in res[t])
         b0, i0, c0 = _alone(g, Q, s, T, fp16)
         assert np.array_equal(bits, b0) and np.array_equal(it, i0) and np.array_equal(conv, c0)
+        summ = _oracle_parity(req, (bits, it, conv), fp16=fp16)
+        print("request", g.info["n"], "oracle parity", summ, flush=True)
     assert any(res[t][2].cpu().numpy().any() for t in tickets)     # some frames converged
     eng.close()
 
@@ -140,9 +156,11 @@ def test_engine_edge_cases(ldpc, oracle_mod):
     eng.close()
 
 
-def test_serving_results_same_alone_and_in_the_mix(ldpc):
+def test_serving_results_same_alone_and_in_the_mix(ldpc, oracle_mod):
     """A Poisson trace of mixed-code requests served with continuous batching:
-    every request's outputs equal the same request decoded alone."""
+    every request's outputs equal the same request decoded alone, and meet
+    the oracle's parity contract on inputs redrawn on the host (syndromes by
+    the oracle)."""
     import copy
     from paper_1702_07740_amd import serve
     pools = serve.make_pools(ldpc, torch, lifts=(64, 128), frames_per_pool=8)
@@ -159,16 +177,31 @@ def test_serving_results_same_alone_and_in_the_mix(ldpc):
     for i in range(len(trace)):
         for u, v in zip(mixed[i], alone[i]):
             assert np.array_equal(u, v), f"request {i} differs"
+    # every served request against the oracle
+    host = {}
+    for k, P in enumerate(pools):
+        o = oracle_mod.OracleCode(P.code.base, P.Z)
+        x, Q = serve.pool_frames(P.rate, P.Z, o.n, 8)
+        host[k] = (o, Q, o.syndrome(x))
+    conv_total = 0
+    for r in trace:
+        o, Q, s = host[r.pool]
+        a, b = r.frames[0], r.frames[-1] + 1
+        bits, it, conv = mixed[r.index]
+        ref = o.decode(Q[a:b], s[a:b], r.max_iters)
+        check_decode_parity(o, Q[a:b], s[a:b], bits, it, conv, ref, r.max_iters)
+        conv_total += int(conv.sum())
+    assert conv_total > 0
 
 
 @pytest.mark.parametrize("cpt", [1, 2])
 def test_engine_schedule_does_not_change_results(ldpc, oracle_mod, cpt):
-    reqs = _requests(ldpc, oracle_mod, 4)[:4]
+    reqs = [r for i, r in enumerate(_requests(ldpc, oracle_mod, 4)) if i in (0, 1, 2, 3, 8)]
     eng = ldpc.Engine(1 << 30, max_slots=8, checks_per_thread=cpt)
     _say("engine schedule", cpt)
-    tickets = [eng.submit(g, Q, s, T) for g, Q, s, T in reqs]
+    tickets = [eng.submit(g, Q, s, T) for g, Q, s, T, *_ in reqs]
     res = eng.drain(tickets)
-    for (g, Q, s, T), t in zip(reqs, tickets):
+    for (g, Q, s, T, *_), t in zip(reqs, tickets):
         b0, i0, c0 = _alone(g, Q, s, T, False)
         assert np.array_equal(res[t][0].cpu().numpy(), b0)
         assert np.array_equal(res[t][1].cpu().numpy(), i0)
