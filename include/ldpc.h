@@ -181,6 +181,35 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F,
                       void *stream);
 
 /*
+ * ldpc_decode_batch for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, semantics and results as ldpc_decode_batch,
+ * without the workspace: the decode state lives in a fixed scratch region
+ * inside the library, one per device, of LDPC_NOALLOC_SCRATCH_BYTES (part of
+ * the library's device code: the loader places it, and each device the
+ * library runs on holds it until the process ends).  Its address is looked
+ * up at the first ldpc_code_create on a device (again at the first call
+ * here if that failed).  This call allocates and frees nothing, host or
+ * device.
+ * Limit: ldpc_workspace_bytes(code, F, max_iters, opts) must not exceed
+ * LDPC_NOALLOC_SCRATCH_BYTES, else LDPC_EWORKSPACE and nothing is enqueued
+ * (e.g. up to 4 frames of the n = 1,000,050 rate-0.02 code, any frame count
+ * up to about 500 of n = 9,600).
+ * Concurrency: all calls on one device share that device's region, which
+ * keeps the last call's contents (a decode reads only what it has written
+ * itself first).  Calls whose work overlaps on the device -- on different
+ * streams, or from several host threads -- race on it and give undefined
+ * results; serialise them (one stream, or events between streams).
+ * Errors: as ldpc_decode_batch (LDPC_EWORKSPACE for the size limit;
+ * LDPC_EDEVICE if the region's address cannot be found).
+ */
+#define LDPC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ldpc_decode_batch_noalloc(const ldpc_code *code, int32_t F,
+                              const float *llr, const uint8_t *syndrome, int32_t max_iters,
+                              uint8_t *bits_out, int32_t *iters_out, uint8_t *converged_out,
+                              const ldpc_decode_opts *opts, void *stream);
+
+/*
  * s = H x mod 2 for F words.
  *   bits     device [F][n] uint8 (only bit 0 of each byte is used)
  *   syn_out  device [F][m] uint8, values 0/1

@@ -6,6 +6,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <cstring>
 #include <string>
@@ -35,6 +36,38 @@ int fail_with(int status, const char *fmt, ...) {
     va_end(ap);
     g_last_error = buf;
     return status;
+}
+
+// Decode workspace of ldpc_decode_batch_noalloc: one fixed region per device,
+// part of this library's device code (the loader places it with the code and
+// it stays until the process ends).  In host code the name `scratch` is only a
+// host-side stand-in; the region's device address on each device comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+constexpr size_t kScratchBytes = LDPC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_lock;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Look up (once) the scratch region's address on `device`, which must be
+// the current device.
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(g_scratch_lock);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 255)) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> guard(g_scratch_lock);
+    return g_scratch_ptr[device];
 }
 
 int check_device(const ldpc_code *code) {
@@ -309,6 +342,9 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         return fail_with(LDPC_EDEVICE, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
     }
     code->lds_limit = lds > 0 ? (size_t)lds : 0;
+    // set-up of the no-allocation decode on this device (its failure is
+    // reported by ldpc_decode_batch_noalloc, which retries the lookup)
+    (void)scratch_setup(code->device);
     e = hipMalloc(reinterpret_cast<void **>(&code->table), host.size() * sizeof(int32_t));
     if (e != hipSuccess) {
         delete code;
@@ -481,10 +517,16 @@ int ldpc_decode_schedule(const ldpc_code *code, int32_t F, const ldpc_decode_opt
     return LDPC_OK;
 }
 
-int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const uint8_t *syndrome,
+}  // extern "C"
+
+namespace {
+
+// The body of both decode entry points.  noalloc: `workspace` is ignored and
+// the decode runs in the device's fixed scratch region.
+int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const uint8_t *syndrome,
                       int32_t max_iters, uint8_t *bits_out, int32_t *iters_out,
                       uint8_t *converged_out, const ldpc_decode_opts *opts, void *workspace,
-                      size_t workspace_bytes, void *stream) {
+                      size_t workspace_bytes, void *stream, bool noalloc) {
     if (!code) return fail_with(LDPC_EINVAL, "code is null");
     if (F < 1 || F > 65535) return fail_with(LDPC_EINVAL, "F = %d outside [1, 65535]", F);
     if (max_iters < 0) return fail_with(LDPC_EINVAL, "max_iters = %d < 0", max_iters);
@@ -505,14 +547,32 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const 
         return fail_with(LDPC_EINVAL, "(max_iters + 1) * F too large");
     const size_t need = ldpc::work_layout(code->dev, F, max_iters, o.msg_fp16 != 0,
                                           o.llr_out != nullptr).total;
-    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    if (noalloc) {
+        if (need > kScratchBytes)
+            return fail_with(LDPC_EWORKSPACE,
+                             "decode needs %zu bytes of state; the no-allocation scratch region "
+                             "holds %zu (fewer frames or iterations per call)",
+                             need, kScratchBytes);
+    } else if (!workspace || workspace_bytes < need ||
+               (reinterpret_cast<uintptr_t>(workspace) & 255)) {
         return fail_with(LDPC_EWORKSPACE, "workspace %p of %zu bytes; need %zu bytes, 256-aligned",
                          workspace, workspace_bytes, need);
+    }
     int sched = 0;
     int st = resolve_schedule(code, F, o, &sched);
     if (st != LDPC_OK) return st;
     st = check_device(code);
     if (st != LDPC_OK) return st;
+    if (noalloc) {
+        workspace = scratch_ptr(code->device);
+        if (!workspace) {
+            const hipError_t e = scratch_setup(code->device);
+            if (e != hipSuccess)
+                return fail_with(LDPC_EDEVICE, "scratch region: hipGetSymbolAddress: %s",
+                                 hipGetErrorString(e));
+            workspace = scratch_ptr(code->device);
+        }
+    }
 
     ldpc::DecodeLaunch l{};
     l.c = code->dev;
@@ -538,6 +598,26 @@ int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const 
                        : ldpc::enqueue_decode(l);
     if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
     return LDPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldpc_decode_batch(const ldpc_code *code, int32_t F, const float *llr, const uint8_t *syndrome,
+                      int32_t max_iters, uint8_t *bits_out, int32_t *iters_out,
+                      uint8_t *converged_out, const ldpc_decode_opts *opts, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+    return decode_batch_impl(code, F, llr, syndrome, max_iters, bits_out, iters_out, converged_out,
+                             opts, workspace, workspace_bytes, stream, false);
+}
+
+int ldpc_decode_batch_noalloc(const ldpc_code *code, int32_t F, const float *llr,
+                              const uint8_t *syndrome, int32_t max_iters, uint8_t *bits_out,
+                              int32_t *iters_out, uint8_t *converged_out,
+                              const ldpc_decode_opts *opts, void *stream) {
+    return decode_batch_impl(code, F, llr, syndrome, max_iters, bits_out, iters_out, converged_out,
+                             opts, nullptr, 0, stream, true);
 }
 
 int ldpc_syndrome(const ldpc_code *code, int32_t F, const uint8_t *bits, uint8_t *syn_out,

@@ -28,8 +28,9 @@ EXPORTS = (
     "ldpc_workspace_bytes", "ldpc_decode_batch", "ldpc_syndrome", "ldpc_status_string",
     "ldpc_last_error", "ldpc_reconciliation_llr", "ldpc_reconciliation_message",
     "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_request_bytes", "ldpc_engine_submit",
-    "ldpc_engine_step", "ldpc_engine_poll", "ldpc_decode_schedule",
+    "ldpc_engine_step", "ldpc_engine_poll", "ldpc_decode_schedule", "ldpc_decode_batch_noalloc",
 )
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 SCHEDULE_AUTO, SCHEDULE_LAUNCHES, SCHEDULE_RESIDENT = 0, 1, 2
 _SCHEDULES = {"auto": SCHEDULE_AUTO, "launches": SCHEDULE_LAUNCHES, "resident": SCHEDULE_RESIDENT}
@@ -97,6 +98,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.ldpc_decode_batch.restype = ctypes.c_int
         lib.ldpc_decode_batch.argtypes = [P, I32, P, P, I32, P, P, P,
                                           ctypes.POINTER(DecodeOpts), P, ctypes.c_size_t, P]
+        lib.ldpc_decode_batch_noalloc.restype = ctypes.c_int
+        lib.ldpc_decode_batch_noalloc.argtypes = [P, I32, P, P, I32, P, P, P,
+                                                  ctypes.POINTER(DecodeOpts), P]
         lib.ldpc_decode_schedule.restype = ctypes.c_int
         lib.ldpc_decode_schedule.argtypes = [P, I32, ctypes.POINTER(DecodeOpts), ctypes.POINTER(I32)]
         lib.ldpc_syndrome.restype = ctypes.c_int
@@ -253,6 +257,36 @@ class Code:
             workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
         _check(st, "ldpc_decode_batch")
         return bits, iters, conv, L
+
+    def decode_noalloc(self, llr, syndrome, max_iters: int, early_stop=True, check_from_iter=0,
+                       msg_fp16=False, out=None, stream=None, checks_per_thread=0,
+                       schedule="auto"):
+        """ldpc_decode_batch_noalloc: as ``decode`` (no posteriors), with the decode
+        state in the library's fixed per-device scratch region instead of a
+        workspace.  ``out`` = (bits, iters, converged) preallocated tensors, else
+        they are allocated here (the library call itself allocates nothing)."""
+        import torch
+        if llr.dtype != torch.float32 or syndrome.dtype != torch.uint8:
+            raise TypeError("llr must be float32 and syndrome uint8")
+        if not (llr.is_cuda and syndrome.is_cuda):
+            raise TypeError("llr and syndrome must be device tensors")
+        if llr.dim() != 2 or llr.shape[1] != self.n or syndrome.shape != (llr.shape[0], self.m):
+            raise ValueError("expected llr [F][n] and syndrome [F][m]")
+        llr = llr.contiguous()
+        syndrome = syndrome.contiguous()
+        F = llr.shape[0]
+        if out is None:
+            out = (torch.empty((F, self.n), dtype=torch.uint8, device=llr.device),
+                   torch.empty(F, dtype=torch.int32, device=llr.device),
+                   torch.empty(F, dtype=torch.uint8, device=llr.device))
+        bits, iters, conv = out[:3]
+        opts = make_opts(early_stop, check_from_iter, msg_fp16, None, None, checks_per_thread,
+                         schedule)
+        st = load().ldpc_decode_batch_noalloc(
+            self._h, F, llr.data_ptr(), syndrome.data_ptr(), int(max_iters), bits.data_ptr(),
+            iters.data_ptr(), conv.data_ptr(), ctypes.byref(opts), _stream_handle(stream))
+        _check(st, "ldpc_decode_batch_noalloc")
+        return bits, iters, conv
 
     def syndrome(self, bits, stream=None):
         """H x mod 2 for uint8 words [F][n] (CUDA tensor) -> uint8 [F][m]."""
