@@ -40,7 +40,7 @@ PAPER_KRAW_MBPS = 1.72       # GTX 1080, q=21 QC code, Table II (context only)
 # fingerprint differ and the figure is reported as null.
 KERNEL_SOURCES = ("internal.h", "passes.h", "decoder.hip")
 MEASURED_TRAFFIC = {
-    "check_pass": {"sources": "3ab4f9d631364180", "fetch_kib": 50789.5, "write_kib": 64746.3,
+    "check_pass_F8": {"sources": "3ab4f9d631364180", "fetch_kib": 50789.5, "write_kib": 64746.3,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
@@ -92,19 +92,19 @@ class HipEvents:
             self.lib.hipEventDestroy(self.arr[i])
 
 
-def run_decodes(torch, code, dQ, ds, T, steps, warmup, fp16, F):
+def run_decodes(torch, code, dQ, ds, T, steps, warmup, fp16, F, schedule="auto"):
     ws = code.alloc_workspace(F, T, msg_fp16=fp16)
     out = (torch.empty((F, code.n), dtype=torch.uint8, device="cuda"),
            torch.empty(F, dtype=torch.int32, device="cuda"),
            torch.empty(F, dtype=torch.uint8, device="cuda"), None)
     for _ in range(warmup):
-        code.decode(dQ, ds, T, msg_fp16=fp16, workspace=ws, out=out)
+        code.decode(dQ, ds, T, msg_fp16=fp16, workspace=ws, out=out, schedule=schedule)
     torch.cuda.synchronize()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     evs[0].record()
     for k in range(steps):
-        code.decode(dQ, ds, T, msg_fp16=fp16, workspace=ws, out=out)
+        code.decode(dQ, ds, T, msg_fp16=fp16, workspace=ws, out=out, schedule=schedule)
         evs[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -112,7 +112,16 @@ def run_decodes(torch, code, dQ, ds, T, steps, warmup, fp16, F):
     total_ms = evs[0].elapsed_time(evs[steps])
     iters = out[1].cpu().numpy()
     conv = out[2].cpu().numpy()
-    return {"total_ms": total_ms, "per_ms": per, "wall_s": wall, "iters": iters, "conv": conv}
+    return {"total_ms": total_ms, "per_ms": per, "wall_s": wall, "iters": iters, "conv": conv,
+            "bits": out[0].cpu().numpy()}
+
+
+def frame_errors(bits, x):
+    """Frames whose decoded word differs from the key anywhere (a frame that
+    converged to another word of the same syndrome coset counts as an error)."""
+    k = int(np.sum(np.any(bits != x, axis=1)))
+    F = int(x.shape[0])
+    return {"frame_errors": k, "frames": F, "fer": k / F, "ci95": wilson(k, F)}
 
 
 def kernel_roofline(torch, code, dQ, ds, T, steps, F, info):
@@ -127,7 +136,7 @@ def kernel_roofline(torch, code, dQ, ds, T, steps, F, info):
     cn_ms = np.zeros(T)
     vn_ms = np.zeros(T)
     for _ in range(steps):
-        code.decode(dQ, ds, T, workspace=ws, out=out, timing_events=ev.arr)
+        code.decode(dQ, ds, T, workspace=ws, out=out, timing_events=ev.arr, schedule="launches")
         torch.cuda.synchronize()
         for t in range(1, T + 1):
             cn_ms[t - 1] += ev.elapsed_ms(4 * (t - 1), 4 * (t - 1) + 1)
@@ -161,6 +170,88 @@ def kernel_roofline(torch, code, dQ, ds, T, steps, F, info):
     }
 
 
+def algorithmic_bytes(info, fp16=False):
+    """Algorithmic bytes per frame of the steady check pass and of the variable
+    pass: every stored message read and written once by the check pass, the
+    degree-1 inputs and the packed syndrome bits; the variable pass reads every
+    message once and the core channel LLRs and writes the core totals (core
+    totals gathered by the check pass are a few hundred KB per frame, taken as
+    cache-resident)."""
+    w = 2 if fp16 else 4
+    Z, E_state, NC, m = info["Z"], info["state_edges"], info["core_cols"], info["m"]
+    cn = 2 * w * E_state + 4 * info["deg1_cols"] * Z + m / 8
+    vn = w * E_state + 8 * NC * Z
+    return cn, vn
+
+
+def roofline_entry(kr, F, where):
+    """The roofline object of the dominant kernel (the check pass) from the
+    per-kernel events of kernel_roofline."""
+    dom = max(kr, key=lambda k: kr[k]["share"])
+    return {"bound": "hbm", "kernel": dom, "achieved": round(kr[dom]["achieved_GBs"], 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(kr[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(f"{dom}_F{F}"),
+            "algorithmic_bytes": kr[dom]["bytes_per_launch"], "avg_ms": kr[dom]["avg_ms"],
+            "working_set": where, "kernels": kr}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads() -> int:
+    """Host threads this process may run on (its CPU affinity), else the CPU count."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+def end_to_end(torch, code, x, Q, T, steps, F):
+    """Decode time including the transfers (Table IV's latency includes them):
+    LLRs and syndromes from pinned host memory to the device, the decode, and
+    bits, iteration counts and flags back to pinned host memory, one stream."""
+    hQ = torch.from_numpy(Q).pin_memory()
+    hx = torch.from_numpy(x).pin_memory()
+    dQ = torch.empty_like(hQ, device="cuda")
+    dx = hx.cuda()
+    hs = code.syndrome(dx).cpu().pin_memory()
+    ds = torch.empty_like(hs, device="cuda")
+    ws = code.alloc_workspace(F, T)
+    out = (torch.empty((F, code.n), dtype=torch.uint8, device="cuda"),
+           torch.empty(F, dtype=torch.int32, device="cuda"),
+           torch.empty(F, dtype=torch.uint8, device="cuda"), None)
+    hb = torch.empty((F, code.n), dtype=torch.uint8).pin_memory()
+    hi = torch.empty(F, dtype=torch.int32).pin_memory()
+    hc = torch.empty(F, dtype=torch.uint8).pin_memory()
+
+    def once():
+        dQ.copy_(hQ, non_blocking=True)
+        ds.copy_(hs, non_blocking=True)
+        code.decode(dQ, ds, T, workspace=ws, out=out)
+        hb.copy_(out[0], non_blocking=True)
+        hi.copy_(out[1], non_blocking=True)
+        hc.copy_(out[2], non_blocking=True)
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        once()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_step": ms, "mbit_s": F * code.n / (ms * 1e-3) / 1e6,
+            "transfer_bytes": int(hQ.numel() * 4 + hs.numel() + hb.numel() + 5 * F)}
+
+
 def cpu_baseline(base, Z, n, snr, seed, threads, iters_sample):
     """The FP64 oracle as it stands, on `threads` frames of the same workload x
     `iters_sample` iterations (early stop off), scaled to the metric's 100
@@ -175,8 +266,10 @@ def cpu_baseline(base, Z, n, snr, seed, threads, iters_sample):
     wall = time.perf_counter() - t0
     mbps = threads * n * iters_sample / (wall * 100.0) / 1e6
     return {"value": mbps, "unit": "Mbit/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
             "sample": f"{threads} frames x {iters_sample} iterations of n={n}, early stop off, "
-                      f"{wall:.1f} s wall on {threads} threads, scaled to 100 iterations"}
+                      f"one frame per thread, {wall:.1f} s wall on {threads} threads "
+                      f"({wall * threads:.0f} s of CPU work), scaled to 100 iterations"}
 
 
 def wilson(k, n, z=1.959964):
@@ -431,6 +524,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-hbm-point", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--workload", default="decode",
                     choices=["decode", "mixed", "frontend", "serving", "small"],
                     help="decode: the n=1,000,050 headline; mixed: 64 frames of 9 codes in one "
@@ -471,7 +566,9 @@ def main():
     base = synth.template_base(144, Z, seed=1)
     code = ldpc.Code(base, Z)
     n, m = code.n, code.m
-    print(f"[bench] code n={n} m={m} frames={F} snr={args.snr} T={T}", file=sys.stderr, flush=True)
+    schedule = code.schedule(F=F)
+    print(f"[bench] code n={n} m={m} frames={F} snr={args.snr} T={T} schedule={schedule}",
+          file=sys.stderr, flush=True)
     x, Q = synth.biawgn_frames(n, F, args.snr, seed=2026)
     dQ = torch.from_numpy(Q).cuda()
     ds = code.syndrome(torch.from_numpy(x).cuda())
@@ -480,6 +577,8 @@ def main():
     r32 = run_decodes(torch, code, dQ, ds, T, args.steps, args.warmup, False, F)
     print(f"[bench] fp32 done {r32['total_ms']:.1f} ms", file=sys.stderr, flush=True)
     value = F * n * args.steps / (r32["total_ms"] * 1e-3) / 1e6
+    fe32 = frame_errors(r32["bits"], x)
+    info = code.info
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mbit/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -489,14 +588,15 @@ def main():
         "config": {"workload": "QC multi-edge R=0.02 template, Z=6667 (n=1,000,050), "
                                f"{F} BIAWGN frames at {args.snr} dB, max {T} iterations, early stop",
                    "n": n, "Z": Z, "rate": 0.02, "frames": F, "snr_db": args.snr,
-                   "max_iters": T, "early_stop": True, "messages": "fp32"},
+                   "max_iters": T, "early_stop": True, "messages": "fp32", "schedule": schedule},
         "latency_ms": {"p50": float(np.percentile(r32["per_ms"], 50)),
                        "p99": float(np.percentile(r32["per_ms"], 99))},
-        "fer": float(1.0 - np.mean(r32["conv"])),
+        "fer": fe32["fer"], "fer_detail": fe32,
         "avg_iters": float(np.mean(r32["iters"])),
+        # information throughput K' = K_raw R (1 - FER) (Sec. IV-A)
+        "info_mbit_s": round(value * 0.02 * (1.0 - fe32["fer"]), 6),
         "context": {"paper_gtx1080_kraw_mbit_s": PAPER_KRAW_MBPS},
     }
-    info = code.info
     # whole-path roofline: algorithmic bytes per frame-iteration (every stored
     # message read and written once, all channel LLRs, the syndrome bits)
     b_min = 8 * info["state_edges"] + 4 * n + m / 8
@@ -510,26 +610,53 @@ def main():
     if not args.no_fp16:
         r16 = run_decodes(torch, code, dQ, ds, T, args.steps, args.warmup, True, F)
         v16 = F * n * args.steps / (r16["total_ms"] * 1e-3) / 1e6
+        fe16 = frame_errors(r16["bits"], x)
         res["fp16"] = {"value": round(v16, 3), "ms_per_step": r16["total_ms"] / args.steps,
                        "p99_ms": float(np.percentile(r16["per_ms"], 99)),
-                       "fer": float(1.0 - np.mean(r16["conv"])),
-                       "avg_iters": float(np.mean(r16["iters"]))}
+                       "fer": fe16["fer"], "fer_detail": fe16,
+                       "avg_iters": float(np.mean(r16["iters"])),
+                       "schedule": code.schedule(F=F, msg_fp16=True)}
         print(f"[bench] fp16 done {r16['total_ms']:.1f} ms", file=sys.stderr, flush=True)
 
     if not args.no_roofline:
-        kr = kernel_roofline(torch, code, dQ, ds, T, max(2, min(args.steps, 5)), F, info)
-        dom = max(kr, key=lambda k: kr[k]["share"])
-        res["roofline"] = {"bound": "hbm", "kernel": dom,
-                           "achieved": round(kr[dom]["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": round(kr[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic(dom),
-                           "algorithmic_bytes": kr[dom]["bytes_per_launch"],
-                           "avg_ms": kr[dom]["avg_ms"], "kernels": kr}
+        steps_r = max(2, min(args.steps, 5))
+        kr = kernel_roofline(torch, code, dQ, ds, T, steps_r, F, info)
+        res["roofline"] = roofline_entry(kr, F, "cache-resident: about 131 MB of decode state and "
+                                                "inputs for 8 frames, inside the 256 MB Infinity "
+                                                "Cache")
         print("[bench] roofline done", file=sys.stderr, flush=True)
 
+    if not args.no_hbm_point:
+        # an HBM-resident point: 32 frames (about 525 MB of decode state and
+        # inputs, twice the Infinity Cache), same decode
+        F2 = 32
+        x2, Q2 = synth.biawgn_frames(n, F2, args.snr, seed=2027)
+        dQ2 = torch.from_numpy(Q2).cuda()
+        ds2 = code.syndrome(torch.from_numpy(x2).cuda())
+        steps2 = max(2, min(args.steps, 5))
+        r2 = run_decodes(torch, code, dQ2, ds2, T, steps2, 1, False, F2)
+        kr2 = kernel_roofline(torch, code, dQ2, ds2, T, 2, F2, info)
+        v2 = F2 * n * steps2 / (r2["total_ms"] * 1e-3) / 1e6
+        res["hbm_point"] = {
+            "frames": F2, "value": round(v2, 3), "ms_per_step": r2["total_ms"] / steps2,
+            "path_roofline_frac": b_min * float(np.sum(r2["iters"])) * steps2
+            / (r2["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "roofline": roofline_entry(kr2, F2, "HBM-resident: about 525 MB, twice the "
+                                                "Infinity Cache")}
+        del dQ2, ds2
+        print("[bench] hbm point done", file=sys.stderr, flush=True)
+
+    if not args.no_e2e:
+        e2e = end_to_end(torch, code, x, Q, T, max(2, min(args.steps, 5)), F)
+        res["end_to_end"] = {"mbit_s": round(e2e["mbit_s"], 3), "ms_per_step": e2e["ms_per_step"],
+                             "includes": "LLR and syndrome upload from pinned host memory, "
+                                         "decode, bits/iterations/flags download"}
+        print("[bench] end to end done", file=sys.stderr, flush=True)
+
     if not args.no_cpu_baseline:
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = cpu_threads()
         res["cpu_baseline"] = cpu_baseline(base, Z, n, args.snr, 2026, threads, 8)
+        res["cpu_baseline"]["gpu_over_oracle"] = round(value / res["cpu_baseline"]["value"], 1)
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
 
     print(json.dumps(res), flush=True)
