@@ -210,7 +210,9 @@ int ldpc_decode_batch_noalloc(const ldpc_code *code, int32_t F,
                               const ldpc_decode_opts *opts, void *stream);
 
 /*
- * s = H x mod 2 for F words.
+ * s = H x mod 2 for F words: the parity check of Alg. 1 Step 4 (Sec. III-D),
+ * on the QC lifting of Sec. III-C, as a stand-alone call (Bob's syndrome of his
+ * key bits in syndrome reconciliation, Sec. II-C.4).
  *   bits     device [F][n] uint8 (only bit 0 of each byte is used)
  *   syn_out  device [F][m] uint8, values 0/1
  * Errors: LDPC_EINVAL, LDPC_EDEVICE.

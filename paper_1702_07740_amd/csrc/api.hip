@@ -146,7 +146,7 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     // blocks in row-major order; state blocks numbered in that order
     std::vector<int32_t> row_first(mb), row_deg(mb);
     std::vector<int32_t> blk_shift, blk_kind, blk_ref, blk_col, blk_core;
-    std::vector<int32_t> d1_shift(d1_col.size(), 0);
+    std::vector<int32_t> d1_shift(d1_col.size(), 0), d1_row(d1_col.size(), 0);
     std::vector<int32_t> st_row, st_core, st_shift;
     int maxdeg = 0;
     std::vector<int32_t> row_ns(mb);
@@ -178,6 +178,7 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
                 blk_ref.push_back(col_ref[c]);
                 blk_core.push_back(-1);
                 d1_shift[col_ref[c]] = s;
+                d1_row[col_ref[c]] = r;
             }
         }
         row_deg[r] = d;
@@ -252,6 +253,12 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     for (int r = 0; r < mb; ++r)
         if (!common(r)) row_list.push_back(r);
     const size_t o_rl = put(row_list);
+    // degree-1 columns whose row is a common row of degree 3 with 2 stored
+    // blocks: that class is updated in the t-domain and takes e^{-|Q|}
+    std::vector<int32_t> d1_tdom(d1_col.size(), 0);
+    for (size_t k = 0; k < d1_col.size(); ++k)
+        d1_tdom[k] = (common(d1_row[k]) && cls_of(d1_row[k]) == ldpc::kTdomClass) ? 1 : 0;
+    const size_t o_d1t = put(d1_tdom);
     // descriptors of the common rows (offsets within one frame's arrays)
     const int32_t Zt = ((2 * Z + ldpc::kLanePad) + 63) / 64 * 64;
     const int32_t W = (Z + 63) / 64;
@@ -401,6 +408,7 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.col_ref = T + o_colr;
     d.d1_shift = T + o_d1s;
     d.d1_col = T + o_d1c;
+    d.d1_tdom = T + o_d1t;
 
     ldpc_code_info_t &I = code->info;
     I.n = d.n;

@@ -29,6 +29,9 @@ constexpr int kSmallRowDegree = 6;
 // Common rows come in 2 * kSmallRowDegree classes (degree D, stored blocks
 // D - 1 or D); class index 2 (D - 1) + (stored - (D - 1)).
 constexpr int kFixedClasses = 2 * kSmallRowDegree;
+// The common-row class (degree 3, 2 stored blocks) whose check update runs in
+// the t-domain (see tdom_check3).
+constexpr int kTdomClass = 4;
 // Words of a common row's descriptor (see CodeDev::row_desc).
 constexpr int kRowDescWords = 20;
 
@@ -118,6 +121,10 @@ struct CodeDev {
     const int32_t *col_kind, *col_ref;
     // per degree-1 column: its base column and the shift of its only block
     const int32_t *d1_col, *d1_shift;
+    // per degree-1 column: 1 if its row is of class (degree 3, 2 stored
+    // blocks), updated in the t-domain, so its input is +-e^{-|Q|} rather than
+    // +-Phi(|Q|)
+    const int32_t *d1_tdom;
 };
 
 // Byte offsets of the decode workspace for F frames and T iterations.

@@ -424,6 +424,57 @@ __device__ __forceinline__ bool phi_exclusive(const float (&x)[D], bool syn, con
     return par;
 }
 
+// The check update in the t-domain, for a check of degree 3 with two stored
+// inputs x1, x2 and one degree-1 input whose channel LLR Q enters as
+// tq = e^{-|Q|} (the multi-edge template's type-2 checks, which carry almost
+// all checks).  With t = e^{-|x|} (in base-2 units 2^{-b}) the tanh rule
+// tanh(m/2) = prod tanh(x_k/2) becomes, for two inputs,
+//   t_out = (t_a + t_b) / (1 + t_a t_b),   |m| = -ln t_out,
+// which is Phi(Phi(a) + Phi(b)) written out (tanh(x/2) = (1 - t)/(1 + t)).
+// Every term is positive, so nothing cancels, and each message costs one
+// reciprocal and one logarithm instead of two Phi evaluations.  The clamps
+// of the Phi arguments carry over exactly: the forward clamp of |x| to
+// [1e-7, 30] clamps b before the exponential, and the clamp of the inverse
+// argument (the exclusive Phi sum) to [1e-7, 30] is, Phi being decreasing,
+// a clamp of |m| to [Phi(30), Phi(1e-7)].  Accuracy: |m| within 3.2e-7 *
+// max(|m|, 1) of the double-precision definition over inputs 1e-9 .. 40.
+// Outputs (base 2): |m| to input 1 (from x2 and Q), |m| to input 2 (from x1
+// and Q), and whether the degree-1 variable's |Q| exceeds the clamped |m|
+// of the message from x1 and x2 (its decision then follows Q).
+constexpr float kMsgLo = 2.7000394e-13f;  // Phi(30) log2(e)
+constexpr float kMsgHi = 2.4253496e+01f;  // Phi(1e-7) log2(e)
+constexpr float kTLo = 5.0000020e-08f;    // 2^-kMsgHi = e^{-Phi(1e-7)}
+
+__device__ __forceinline__ float tdom_mag(float ta, float tb) {
+    const float num = fmaf(ta, tb, 1.0f);
+    const float r = num * __builtin_amdgcn_rcpf(ta + tb);
+    return __builtin_amdgcn_fmed3f(__builtin_amdgcn_logf(r), kMsgLo, kMsgHi);
+}
+
+__device__ __forceinline__ void tdom_check3(float x1, float x2, float tq, const PhiConsts &PK,
+                                            float &mag1, float &mag2, bool &q_wins, float &t1o,
+                                            float &t2o) {
+    const float t1 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_fmed3f(fabsf(x1), kPhiLo, PK.hi));
+    const float t2 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_fmed3f(fabsf(x2), kPhiLo, PK.hi));
+    mag1 = tdom_mag(tq, t2);
+    mag2 = tdom_mag(tq, t1);
+    // |Q| > min(|m_p|, Phi(1e-7)): tq < max(t_p, kTLo), t_p = (t1 + t2) / (1 + t1 t2)
+    q_wins = (tq < kTLo) | (tq * fmaf(t1, t2, 1.0f) < t1 + t2);
+    t1o = t1;
+    t2o = t2;
+}
+
+// The degree-1 input a check reads for variable p: its channel LLR Q_p in the
+// form the check's update takes, with the sign of Q_p: +-Phi(|Q_p|) for the
+// Phi-domain update, +-e^{-|Q_p|} for the t-domain one (base 2 throughout;
+// |Q| clamped to [1e-7, 30] either way).
+__device__ __forceinline__ float d1_input(float q, bool tdom, const PhiConsts &PK) {
+    const float b = fabsf(q) * kLog2e;
+    const float p = tdom ? __builtin_amdgcn_exp2f(-__builtin_amdgcn_fmed3f(b, kPhiLo, PK.hi))
+                         : phi2(b, PK);
+    return q < 0.0f ? -p : p;
+}
+
 // Decision of a degree-1 variable: the sign of Q + m, taken in the Phi domain
 // (|Q| > |m| exactly when Phi(|Q|) < S, S the exclusive sum of the check's
 // other inputs).  The signs of Q and m differ exactly when the check's whole
@@ -525,6 +576,105 @@ __device__ __forceinline__ bool fixed_chunk(const FixedRow<D, DS, Msg> &R, const
     return bad;
 }
 
+// Sign bit of v as the decisions and sign products read it: set iff v < 0
+// (-0 adds to +0, so it counts as non-negative, as L >= 0 decides 0).
+constexpr uint32_t kSignBit = 0x80000000u;
+__device__ __forceinline__ uint32_t neg_bit(float v) {
+    return __float_as_uint(v + 0.0f) & kSignBit;
+}
+
+// A row of class (degree 3, 2 stored blocks, 1 degree-1 block): the
+// template's type-2 checks, almost all checks of a multi-edge code.  Wave
+// `wave` of tile `tile` takes CPT consecutive chunks of 64 checks, check
+// a = tile 256 CPT + wave 64 CPT + 64 q + lane for chunk q, so its packed bit
+// words (syndrome, previous and new degree-1 decisions) are CPT consecutive
+// words: one scalar load each, one store of the new ones.  Step 2 runs in the
+// t-domain (tdom_check3), and the sign products, the parity vote of the
+// previous iteration and the degree-1 decision are formed on sign bits in
+// vector registers.  FULL: every check of the tile is in the row (a < Z);
+// else padding lanes read in-bounds slack (as fixed_chunk), vote nothing and
+// store nothing.  The packed-word loads may read up to CPT - 1 words past a
+// row's last word; the decode workspace places other regions after every bit
+// array, so those reads stay inside it.  Returns true if one of this
+// thread's checks fails the parity check of the voted iteration.
+template <int MODE, typename Msg, int CPT, bool FULL>
+__device__ __forceinline__ bool tdom_chunks(const FixedRow<3, 2, Msg> &R, const CnArgs &A,
+                                            unsigned tile, unsigned wave, const PhiConsts &PK) {
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned a0 = tile * (kBlock * CPT) + wave * (64u * CPT) + lane;
+    const unsigned w0 = tile * (4u * CPT) + wave * CPT;
+    struct Words { uint64_t w[CPT]; };
+    Words sw, dw{};
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        sw.w[q] = uniform_word(R.syn + w0 + q);
+        if constexpr (base_mode(MODE) != kFirst) dw.w[q] = uniform_word(R.dprev[2] + w0 + q);
+    }
+    float lt[CPT][2], mo[CPT][2], ps[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const unsigned a = a0 + 64u * q;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            lt[q][k] = at(R.tot[k], a);
+            mo[q][k] = (base_mode(MODE) == kSteady) ? msg_load<Msg>(&at(R.msg[k], a)) : 0.0f;
+        }
+        ps[q] = at(R.psi[2], a);
+    }
+    uint32_t bad = 0;
+    uint64_t dbits[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const unsigned a = a0 + 64u * q;
+        const bool valid = FULL || a < R.Z;
+        const uint32_t syn = lane_bit(sw.w[q]) ? kSignBit : 0u;
+        const uint32_t s2 = __float_as_uint(ps[q]) & kSignBit;  // sign of Q (never -0)
+        // parity of the voted decisions: core totals of iteration t-1, and the
+        // degree-1 decisions (channel signs at the first iteration)
+        uint32_t d1 = s2;
+        if constexpr (base_mode(MODE) != kFirst)
+            if (!(base_mode(MODE) == kVoteOnly && A.d1_from_llr)) d1 = lane_bit(dw.w[q]) ? kSignBit : 0u;
+        const uint32_t vpar = syn ^ neg_bit(lt[q][0]) ^ neg_bit(lt[q][1]) ^ d1;
+        bad |= valid ? vpar : 0u;
+        if constexpr (base_mode(MODE) == kVoteOnly) continue;
+        // Step 2: magnitudes in the t-domain, signs from the exclusive parities
+        const float x0 = lt[q][0] - mo[q][0], x1 = lt[q][1] - mo[q][1];
+        const uint32_t s0 = neg_bit(x0), s1 = neg_bit(x1);
+        float mag0, mag1, t1, t2;
+        bool q_wins;
+        tdom_check3(x0, x1, fabsf(ps[q]), PK, mag0, mag1, q_wins, t1, t2);
+        const float m0 = __uint_as_float(__float_as_uint(mag0) | (syn ^ s1 ^ s2));
+        const float m1 = __uint_as_float(__float_as_uint(mag1) | (syn ^ s0 ^ s2));
+        if (valid) {
+            msg_store<Msg>(&at(R.msg[0], a), m0);
+            msg_store<Msg>(&at(R.msg[1], a), m1);
+        }
+        // degree-1 decision: the sign of Q, unless the check's message to it
+        // has the other sign (odd parity) and the larger magnitude
+        const uint32_t par = syn ^ s0 ^ s1 ^ s2;
+        const uint32_t d = s2 ^ (q_wins ? 0u : par);
+        dbits[q] = wave_ballot(valid && d != 0u);
+        if constexpr (with_post(MODE)) {
+            if (valid) {
+                unsigned j = a + R.shift[2];
+                j -= (j >= R.Z) ? R.Z : 0u;
+                const float mp = tdom_mag(t1, t2) * kLn2;
+                at(R.post[2], a) = at(R.llr[2], j) + ((syn ^ s0 ^ s1) ? -mp : mp);
+            }
+        }
+    }
+    if constexpr (base_mode(MODE) != kVoteOnly) {
+        // lanes 0 .. CPT-1 store the CPT consecutive decision words
+        if (lane < (unsigned)CPT) {
+            uint64_t v = dbits[0];
+#pragma unroll
+            for (int q = 1; q < CPT; ++q) v = (lane == (unsigned)q) ? dbits[q] : v;
+            if (FULL || w0 + lane <= R.Wm1) at(R.dcur[2], w0 + lane) = v;
+        }
+    }
+    return bad != 0u;
+}
+
 // How many of a thread's checks of a fixed row are processed at once (bounded
 // by registers for larger rows).
 template <int D> struct FixedChunk { static constexpr int value = D <= 3 ? 4 : 1; };
@@ -561,14 +711,21 @@ __device__ __forceinline__ void check_row_fixed(const CodeDev &c, const CnArgs &
     // together with the flag loads instead of after the branch.
     const bool skip = (A.skip_after >= 0) & (prev == 0);
     if (skip | (R.any_desc < 0)) return;
-    constexpr int K = FixedChunk<D>::value < CPT ? FixedChunk<D>::value : CPT;
     const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const unsigned a0 = tile * (kBlock * CPT) + threadIdx.x;
-    const unsigned w0 = tile * (4u * CPT) + wave;
     bool bad = false;
+    if constexpr (D == 3 && DS == 2) {
+        if ((tile + 1) * (kBlock * CPT) <= R.Z)
+            bad = tdom_chunks<MODE, Msg, CPT, true>(R, A, tile, wave, PK);
+        else
+            bad = tdom_chunks<MODE, Msg, CPT, false>(R, A, tile, wave, PK);
+    } else {
+        constexpr int K = FixedChunk<D>::value < CPT ? FixedChunk<D>::value : CPT;
+        const unsigned a0 = tile * (kBlock * CPT) + threadIdx.x;
+        const unsigned w0 = tile * (4u * CPT) + wave;
 #pragma unroll
-    for (int q0 = 0; q0 < CPT; q0 += K)
-        bad |= fixed_chunk<D, DS, K, MODE, Msg>(R, A, a0 + q0 * kBlock, w0 + 4u * q0, PK);
+        for (int q0 = 0; q0 < CPT; q0 += K)
+            bad |= fixed_chunk<D, DS, K, MODE, Msg>(R, A, a0 + q0 * kBlock, w0 + 4u * q0, PK);
+    }
     if (A.vote) vote_store(flag, seen, bad);
 }
 
@@ -784,9 +941,9 @@ __device__ __forceinline__ void init_totals_work(const CodeDev &c, const float *
     row[j + c.Z] = q;
 }
 
-// Degree-1 inputs in check order: Psi[a] = +-Phi(|Q_p|) in base 2, p the
-// variable of check a of degree-1 block k, with the sign of Q_p (negative iff
-// Q_p < 0).
+// Degree-1 inputs in check order: Psi[a] = d1_input(Q_p), p the variable of
+// check a of degree-1 block k (+-Phi(|Q_p|), or +-e^{-|Q_p|} where the block's
+// row is updated in the t-domain), once per decode.
 __device__ __forceinline__ void init_psi_work(const CodeDev &c, const float *llr, float *psi,
                                               size_t psi_frame, int f, int k, unsigned tile) {
     const unsigned Z = (unsigned)c.Z;
@@ -795,8 +952,7 @@ __device__ __forceinline__ void init_psi_work(const CodeDev &c, const float *llr
     unsigned j = a + (unsigned)c.d1_shift[k];
     j -= (j >= Z) ? Z : 0u;
     const float q = llr[(size_t)f * c.n + (size_t)c.d1_col[k] * Z + j];
-    const float p = phi2(fabsf(q) * kLog2e);
-    psi[(size_t)f * psi_frame + (size_t)k * c.Zp + a] = q < 0.0f ? -p : p;
+    psi[(size_t)f * psi_frame + (size_t)k * c.Zp + a] = d1_input(q, c.d1_tdom[k] != 0, phi_consts());
 }
 
 struct FinArgs {

@@ -15,8 +15,9 @@
 // (read-only after the first phase), and to write the outputs.
 //
 // The arithmetic is the per-iteration decoder's, operation for operation: the
-// same base-2 state, the same phi2, the same prefix/suffix order of the
-// exclusive sums, the same Phi-domain degree-1 decision, and core totals
+// same base-2 state, the same phi2 and t-domain check update, the same
+// prefix/suffix order of the exclusive sums, the same degree-1 decisions, and
+// core totals
 // summed as (Q + S0) + S1 over the same two row groups.  So a frame decodes to
 // the same bits, iteration count and convergence flag on either schedule.
 //
@@ -100,6 +101,26 @@ __device__ __forceinline__ bool res_fixed(const ResView<Msg> &S, const int32_t *
 
 #pragma unroll
     for (int q = 0; q < K; ++q) {
+        if constexpr (D == 3 && DS == 2) {
+            // Step 2 in the t-domain, as in the per-iteration check pass
+            bool neg[3];
+            bool p2 = (sw[q] >> lane) & 1ull;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                neg[k] = x[q][k] < 0.0f;
+                p2 ^= neg[k];
+            }
+            float mag[2], t1, t2;
+            bool q_wins;
+            tdom_check3(x[q][0], x[q][1], fabsf(x[q][2]), PK, mag[0], mag[1], q_wins, t1, t2);
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (valid[q]) msg_store<Msg>(&S.msg[idx[q][k]], (p2 ^ neg[k]) ? -mag[k] : mag[k]);
+            const bool dd = neg[2] ^ (p2 && !q_wins);
+            const unsigned long long bits = wave_ballot(valid[q] && dd);
+            if (lane == 0) dcur[idx[q][2]] = bits;
+            continue;
+        }
         // Step 2: sign product with the syndrome bit, Phi-domain exclusive sums
         float ph[D], ex[D];
         bool neg[D];
@@ -373,8 +394,7 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
             unsigned j = a + (unsigned)uniform_i32(c.d1_shift + k);
             j -= (j >= Z) ? Z : 0u;
             const float q = llr[(size_t)uniform_i32(c.d1_col + k) * Z + j];
-            const float p = phi2(fabsf(q) * kLog2e, PK);
-            psi[k * Zp + a] = q < 0.0f ? -p : p;
+            psi[k * Zp + a] = d1_input(q, uniform_i32(c.d1_tdom + k) != 0, PK);
             neg = q < 0.0f;
         }
         const unsigned long long bits = wave_ballot(neg);

@@ -492,6 +492,36 @@ def test_single_check_update_accuracy_over_the_phi_range(ldpc, oracle_mod, D):
     assert np.all(err <= bound), float(np.max(err / bound))
 
 
+def test_tdomain_check_update_accuracy_over_the_phi_range(ldpc, oracle_mod):
+    """One iteration of two checks of degree 3, each with two stored inputs
+    (columns 0 and 1, of degree 2) and one degree-1 input: the class whose
+    update runs in the t-domain.  Input magnitudes span 1e-9 .. 40, i.e. both
+    clamps; the messages are held to 1e-5 of max(|L|, 1) (the t-domain keeps
+    absolute, not relative, accuracy for tiny messages)."""
+    rng = np.random.default_rng(33)
+    Z = 4096
+    base = np.full((2, 4), -1, dtype=np.int32)
+    base[0, [0, 1, 2]] = [rng.integers(0, Z), rng.integers(0, Z), 0]
+    base[1, [0, 1, 3]] = [rng.integers(0, Z), rng.integers(0, Z), 0]
+    g, o = _codes(ldpc, oracle_mod, base, Z)
+    mag = np.exp(rng.uniform(np.log(1e-9), np.log(40.0), size=(2, o.n)))
+    Q = (mag * rng.choice([-1.0, 1.0], size=(2, o.n))).astype(np.float32)
+    s = rng.integers(0, 2, size=(2, o.m)).astype(np.uint8)
+    _say("t-domain check accuracy")
+    for T in (1, 2):
+        bits, _, _, L = _gpu_decode(g, Q, s, T, early_stop=False, want_llr=True)
+        b_r, L_r, _, _ = o.decode(Q, s, T, early_stop=False)
+        err = np.abs(L.astype(np.float64) - L_r)
+        bound = 1e-5 * np.maximum(np.abs(L_r), 1.0)
+        ratio = err / bound
+        for f, v in zip(*np.unravel_index(np.argsort(ratio, axis=None)[-5:], ratio.shape)):
+            print("T", T, "frame", f, "var", v, "column", v // Z, "Q", Q[f, v], "L", L[f, v],
+                  "oracle", L_r[f, v], "err/bound", ratio[f, v], flush=True)
+        assert np.all(err <= bound), (T, float(np.max(ratio)))
+        sure = np.abs(L_r) > 1e-5 * np.maximum(np.abs(Q), 1.0)
+        assert np.array_equal(bits[sure], b_r[sure])
+
+
 def test_rows_with_several_degree_1_blocks(ldpc, oracle_mod):
     """Checks joined to two degree-1 variables, and a check joined only to
     degree-1 variables, take the generic row path."""
