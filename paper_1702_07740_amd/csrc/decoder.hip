@@ -42,30 +42,32 @@ namespace {
 
 using namespace dev;
 
-// One launch covers the rows of one degree class; grid.y walks that class's
-// rows in the row list.
+// One launch covers the rows of one degree class; item i of the launch is
+// (frame, row, tile) with the tile fastest, decoded with host-computed
+// divisors.
 template <typename Msg, bool kLarge, int MODE, int CPT>
-__device__ __forceinline__ void check_pass_body(const CodeDev &c, const CnArgs &A, unsigned tiles,
-                                                unsigned rows) {
-    const unsigned n = tiles * rows * (unsigned)A.F;
-    unsigned i = xcd_item(blockIdx.x, n);
+__device__ __forceinline__ void check_pass_body(const CodeDev &c, const CnArgs &A, FastDiv tiles,
+                                                FastDiv rows, unsigned frames) {
+    const unsigned n = tiles.d * rows.d * frames;
+    const unsigned i = xcd_item(blockIdx.x, n);
     if (i >= n) return;
-    const unsigned tile = i % tiles;
-    i /= tiles;
-    const int y = (kLarge ? c.n_small : 0) + (int)(i % rows);
-    check_work<Msg, kLarge, MODE, CPT>(c, A, (int)(i / rows), y, tile);
+    const unsigned i1 = fdiv(i, tiles);
+    const unsigned tile = i - i1 * tiles.d;
+    const unsigned f = fdiv(i1, rows);
+    const int y = (kLarge ? c.n_small : 0) + (int)(i1 - f * rows.d);
+    check_work<Msg, kLarge, MODE, CPT>(c, A, (int)f, y, tile);
 }
 
 template <typename Msg, int MODE, int CPT>
-__global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, unsigned tiles,
-                                                     unsigned rows) {
-    check_pass_body<Msg, false, MODE, CPT>(c, A, tiles, rows);
+__global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, FastDiv tiles,
+                                                     FastDiv rows, unsigned frames) {
+    check_pass_body<Msg, false, MODE, CPT>(c, A, tiles, rows, frames);
 }
 
 template <typename Msg, int MODE, int CPT>
-__global__ __launch_bounds__(kBlock) void check_pass_large(CodeDev c, CnArgs A, unsigned tiles,
-                                                           unsigned rows) {
-    check_pass_body<Msg, true, MODE, CPT>(c, A, tiles, rows);
+__global__ __launch_bounds__(kBlock) void check_pass_large(CodeDev c, CnArgs A, FastDiv tiles,
+                                                           FastDiv rows, unsigned frames) {
+    check_pass_body<Msg, true, MODE, CPT>(c, A, tiles, rows, frames);
 }
 
 // Common rows run with the requested checks per thread (1, 2 or 4); the rare
@@ -85,41 +87,44 @@ template <typename Msg, int MODE>
 void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, int cpt, hipStream_t st,
                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
     const bool both = c.n_small > 0 && c.n_large > 0;
+    const unsigned fr = (unsigned)F;
     if (c.n_small > 0) {
         if constexpr (with_post(MODE)) cpt = kDefaultChecksPerThread;
         const unsigned tl = check_tiles(c.Z, cpt), rows = (unsigned)c.n_small;
-        const dim3 g(xcd_grid(tl * rows * (unsigned)F));
+        const dim3 g(xcd_grid(tl * rows * fr));
+        const FastDiv dt = fast_div(tl), dr = fast_div(rows);
         hipEvent_t e1 = both ? nullptr : stop;
         if constexpr (with_post(MODE)) {
             launch_timed(check_pass<Msg, MODE, kDefaultChecksPerThread>, g, st, start, e1, c, a,
-                         tl, rows);
+                         dt, dr, fr);
         } else {
             if (cpt == 1)
-                launch_timed(check_pass<Msg, MODE, 1>, g, st, start, e1, c, a, tl, rows);
+                launch_timed(check_pass<Msg, MODE, 1>, g, st, start, e1, c, a, dt, dr, fr);
             else if (cpt == 2)
-                launch_timed(check_pass<Msg, MODE, 2>, g, st, start, e1, c, a, tl, rows);
+                launch_timed(check_pass<Msg, MODE, 2>, g, st, start, e1, c, a, dt, dr, fr);
             else
-                launch_timed(check_pass<Msg, MODE, 4>, g, st, start, e1, c, a, tl, rows);
+                launch_timed(check_pass<Msg, MODE, 4>, g, st, start, e1, c, a, dt, dr, fr);
         }
     }
     if (c.n_large > 0) {
         const unsigned tl = check_tiles(c.Z, kDefaultChecksPerThread), rows = (unsigned)c.n_large;
         launch_timed(check_pass_large<Msg, MODE, kDefaultChecksPerThread>,
-                     dim3(xcd_grid(tl * rows * (unsigned)F)), st, both ? nullptr : start, stop, c,
-                     a, tl, rows);
+                     dim3(xcd_grid(tl * rows * fr)), st, both ? nullptr : start, stop, c,
+                     a, fast_div(tl), fast_div(rows), fr);
     }
 }
 
 template <int U, typename Msg>
-__global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A, unsigned tiles) {
-    const unsigned n = tiles * (unsigned)c.NC * (unsigned)A.F;
-    unsigned i = xcd_item(blockIdx.x, n);
+__global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A, FastDiv tiles,
+                                                        FastDiv cols, unsigned frames) {
+    const unsigned n = tiles.d * cols.d * frames;
+    const unsigned i = xcd_item(blockIdx.x, n);
     if (i >= n) return;
-    const unsigned tile = i % tiles;
-    i /= tiles;
-    const int f = (int)(i / (unsigned)c.NC);
+    const unsigned i1 = fdiv(i, tiles);
+    const unsigned tile = i - i1 * tiles.d;
+    const unsigned f = fdiv(i1, cols);
     if (A.fail[(size_t)(A.t - 1) * A.F + f] == 0) return;
-    variable_work<U, Msg, vn_vpt<Msg>()>(c, A, f, (int)(i % (unsigned)c.NC), tile);
+    variable_work<U, Msg, vn_vpt<Msg>()>(c, A, (int)f, (int)(i1 - f * cols.d), tile);
 }
 
 template <typename Msg>
@@ -127,12 +132,14 @@ void launch_variable_pass(const CodeDev &c, const VnArgs &v, int F, hipStream_t 
                           hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
     const unsigned tl = variable_tiles(c.Z, vn_vpt<Msg>());
     const dim3 g(xcd_grid(tl * (unsigned)c.NC * (unsigned)F));
+    const FastDiv dt = fast_div(tl), dc = fast_div((unsigned)c.NC);
+    const unsigned fr = (unsigned)F;
     switch (variable_group(c.max_core_deg)) {
-        case 4: launch_timed(variable_pass<4, Msg>, g, st, start, stop, c, v, tl); break;
-        case 8: launch_timed(variable_pass<8, Msg>, g, st, start, stop, c, v, tl); break;
-        case 13: launch_timed(variable_pass<13, Msg>, g, st, start, stop, c, v, tl); break;
-        case 16: launch_timed(variable_pass<16, Msg>, g, st, start, stop, c, v, tl); break;
-        default: launch_timed(variable_pass<26, Msg>, g, st, start, stop, c, v, tl); break;
+        case 4: launch_timed(variable_pass<4, Msg>, g, st, start, stop, c, v, dt, dc, fr); break;
+        case 8: launch_timed(variable_pass<8, Msg>, g, st, start, stop, c, v, dt, dc, fr); break;
+        case 13: launch_timed(variable_pass<13, Msg>, g, st, start, stop, c, v, dt, dc, fr); break;
+        case 16: launch_timed(variable_pass<16, Msg>, g, st, start, stop, c, v, dt, dc, fr); break;
+        default: launch_timed(variable_pass<26, Msg>, g, st, start, stop, c, v, dt, dc, fr); break;
     }
 }
 

@@ -25,6 +25,23 @@ __device__ __forceinline__ unsigned xcd_item(unsigned g, unsigned n) {
     const unsigned per = (n + kXcds - 1) / kXcds;
     return (g % kXcds) * per + g / kXcds;
 }
+// Division by a launch constant d with a multiplier the host computes: for
+// every x < 2^31, floor(x / d) = (x m) >> l with l = 31 + ceil(log2 d) and
+// m = ceil(2^l / d) (the rounding error x (m d - 2^l) / (d 2^l) stays below
+// 2^-ceil(log2 d) <= 1/d).
+struct FastDiv {
+    uint32_t d, m, l;
+};
+inline FastDiv fast_div(uint32_t d) {
+    uint32_t c = 0;
+    while ((1ull << c) < d) ++c;
+    const uint32_t l = 31 + c;
+    return FastDiv{d, (uint32_t)(((1ull << l) + d - 1) / d), l};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv &f) {
+    return (uint32_t)(((uint64_t)x * f.m) >> f.l);
+}
+
 // Units.  On the device every log-likelihood ratio of the decoding state
 // (core totals, messages, degree-1 inputs) is held in base 2: b = L log2(e),
 // the natural-log value L scaled by 1/ln 2.  Channel LLRs come in and
