@@ -32,17 +32,34 @@ METRIC = "raw decoded Mbit/s, n=1e6 R=0.02, 100 iters; p99 latency; FP16 vs FP32
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 PAPER_KRAW_MBPS = 1.72       # GTX 1080, q=21 QC code, Table II (context only)
 
-# HBM traffic of the steady check pass per launch (8 frames of this workload),
-# from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
-# each scaled by what the counter reads for a 1 GiB device copy
+# HBM traffic of the steady check pass per launch of F frames of this
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by what the counter reads for a 1 GiB device copy
 # (FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB: factors 2.0 and 1.0).  It holds
 # only for the kernel sources it was taken on; any change to them makes the
 # fingerprint differ and the figure is reported as null.
 KERNEL_SOURCES = ("internal.h", "passes.h", "decoder.hip")
+MEASURED_SOURCES = "6226262a246d4d5b"
 MEASURED_TRAFFIC = {
-    "check_pass_F8": {"sources": "3ab4f9d631364180", "fetch_kib": 50789.5, "write_kib": 64746.3,
-                   "fetch_scale": 2.0, "write_scale": 1.0},
+    "check_pass_F8": {"fetch_kib": 50792.4, "write_kib": 64746.9, "fetch_scale": 2.0,
+                      "write_scale": 1.0},
+    "check_pass_F32": {"fetch_kib": 202958.8, "write_kib": 258998.1, "fetch_scale": 2.0,
+                       "write_scale": 1.0},
 }
+# Instruction counts of the steady check pass per frame (rocprofv3 --pmc
+# SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32, SQ_INSTS_SALU per 8-frame dispatch,
+# divided by 8): wave64 instructions, transcendentals included in VALU.
+MEASURED_ISSUE = {
+    "check_pass_fp32": {"valu": 7.948e6 / 8, "trans": 0.802e6 / 8, "salu": 7.210e6 / 8},
+    "check_pass_fp16": {"valu": 8.671e6 / 8, "trans": 0.802e6 / 8, "salu": 7.210e6 / 8},
+}
+# VALU issue ceiling: 256 CUs x 4 SIMDs, each issuing one wave64 VALU
+# instruction every 4 cycles, at 2.4 GHz = 614.4 G wave-instructions/s.  A
+# transcendental (exp2, log2, rcp) takes two issue slots on CDNA4 (half the
+# FP32 rate).  The scalar unit issues one instruction per CU and cycle, the
+# same 614.4 G/s.
+VALU_ISSUE_PEAK = 256 * 2.4e9
+TRANS_SLOTS = 2.0
 
 
 def kernel_fingerprint() -> str:
@@ -57,9 +74,26 @@ def kernel_fingerprint() -> str:
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the counters, or None if stale."""
     m = MEASURED_TRAFFIC.get(kernel)
-    if m is None or m["sources"] != kernel_fingerprint():
+    if m is None or MEASURED_SOURCES != kernel_fingerprint():
         return None
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+
+
+def issue_ceiling(kernel: str, F: int, avg_ms: float):
+    """The instruction-issue ceiling of `kernel` for F frames: issue slots
+    (VALU, transcendentals counted twice) over the VALU issue peak, and the
+    scalar instructions over the same rate.  None if the counters are stale."""
+    m = MEASURED_ISSUE.get(kernel)
+    if m is None or MEASURED_SOURCES != kernel_fingerprint():
+        return None
+    slots = F * (m["valu"] + (TRANS_SLOTS - 1.0) * m["trans"])
+    valu_ms = slots / VALU_ISSUE_PEAK * 1e3
+    salu_ms = F * m["salu"] / VALU_ISSUE_PEAK * 1e3
+    ms = max(valu_ms, salu_ms)
+    return {"valu_wave_instr": F * m["valu"], "trans_wave_instr": F * m["trans"],
+            "salu_wave_instr": F * m["salu"], "issue_slots": slots,
+            "peak_G_per_s": VALU_ISSUE_PEAK / 1e9, "valu_min_ms": valu_ms, "salu_min_ms": salu_ms,
+            "min_ms": ms, "frac": ms / avg_ms}
 
 
 class HipEvents:
@@ -124,19 +158,20 @@ def frame_errors(bits, x):
     return {"frame_errors": k, "frames": F, "fer": k / F, "ci95": wilson(k, F)}
 
 
-def kernel_roofline(torch, code, dQ, ds, T, steps, F, info):
+def kernel_roofline(torch, code, dQ, ds, T, steps, F, info, fp16=False):
     """Average durations of the check and variable passes from HIP events
     that the launches record at the start and end of every kernel (on the
     decode stream), over `steps` decodes."""
     ev = HipEvents(4 * T)
-    ws = code.alloc_workspace(F, T)
+    ws = code.alloc_workspace(F, T, msg_fp16=fp16)
     out = (torch.empty((F, code.n), dtype=torch.uint8, device="cuda"),
            torch.empty(F, dtype=torch.int32, device="cuda"),
            torch.empty(F, dtype=torch.uint8, device="cuda"), None)
     cn_ms = np.zeros(T)
     vn_ms = np.zeros(T)
     for _ in range(steps):
-        code.decode(dQ, ds, T, workspace=ws, out=out, timing_events=ev.arr, schedule="launches")
+        code.decode(dQ, ds, T, msg_fp16=fp16, workspace=ws, out=out, timing_events=ev.arr,
+                    schedule="launches")
         torch.cuda.synchronize()
         for t in range(1, T + 1):
             cn_ms[t - 1] += ev.elapsed_ms(4 * (t - 1), 4 * (t - 1) + 1)
@@ -145,55 +180,58 @@ def kernel_roofline(torch, code, dQ, ds, T, steps, F, info):
     iters = out[1].cpu().numpy()
     cn_ms /= steps
     vn_ms /= steps
+    w = 2 if fp16 else 4
     Z = info["Z"]
     E_state = info["state_edges"]
     E_d1 = info["deg1_cols"] * Z
     NC = info["core_cols"]
     m = info["m"]
-    # algorithmic bytes per frame (FP32 messages): each stored message read once
-    # and written once per check pass (written only at t = 1), the degree-1
-    # channel LLRs and the packed syndrome bits; the variable pass reads every
-    # message once, the core channel LLRs, and writes the core totals.
-    cn_bytes = np.array([(4 if t == 1 else 8) * E_state + 4 * E_d1 + m / 8 for t in range(1, T + 1)])
-    vn_bytes = np.full(T, 4 * E_state + 8 * NC * Z, dtype=np.float64)
+    # algorithmic bytes per frame (w-byte messages): each stored message read
+    # once and written once per check pass (written only at t = 1), the
+    # degree-1 inputs and the packed syndrome bits; the variable pass reads
+    # every message once, the core channel LLRs, and writes the core totals.
+    cn_bytes = np.array([(w if t == 1 else 2 * w) * E_state + 4 * E_d1 + m / 8
+                         for t in range(1, T + 1)])
+    vn_bytes = np.full(T, w * E_state + 8 * NC * Z, dtype=np.float64)
     active_cn = np.array([np.sum(iters >= t - 1) for t in range(1, T + 1)])
     active_vn = np.array([np.sum(iters >= t) for t in range(1, T + 1)])
     cn_gbs = float(np.sum(cn_bytes * active_cn) / (np.sum(cn_ms) * 1e-3) / 1e9)
     vn_gbs = float(np.sum(vn_bytes * active_vn) / (np.sum(vn_ms) * 1e-3) / 1e9)
+    tot = np.sum(cn_ms) + np.sum(vn_ms)
     return {
         "check_pass": {"avg_ms": float(np.mean(cn_ms)), "achieved_GBs": cn_gbs,
                        "bytes_per_frame": float(cn_bytes[-1]),
-                       "bytes_per_launch": float(cn_bytes[-1]) * F, "share": float(np.sum(cn_ms) / (np.sum(cn_ms) + np.sum(vn_ms)))},
+                       "bytes_per_launch": float(cn_bytes[-1]) * F,
+                       "share": float(np.sum(cn_ms) / tot)},
         "variable_pass": {"avg_ms": float(np.mean(vn_ms)), "achieved_GBs": vn_gbs,
                           "bytes_per_frame": float(vn_bytes[-1]),
-                          "bytes_per_launch": float(vn_bytes[-1]) * F, "share": float(np.sum(vn_ms) / (np.sum(cn_ms) + np.sum(vn_ms)))},
+                          "bytes_per_launch": float(vn_bytes[-1]) * F,
+                          "share": float(np.sum(vn_ms) / tot)},
     }
 
 
-def algorithmic_bytes(info, fp16=False):
-    """Algorithmic bytes per frame of the steady check pass and of the variable
-    pass: every stored message read and written once by the check pass, the
-    degree-1 inputs and the packed syndrome bits; the variable pass reads every
-    message once and the core channel LLRs and writes the core totals (core
-    totals gathered by the check pass are a few hundred KB per frame, taken as
-    cache-resident)."""
-    w = 2 if fp16 else 4
-    Z, E_state, NC, m = info["Z"], info["state_edges"], info["core_cols"], info["m"]
-    cn = 2 * w * E_state + 4 * info["deg1_cols"] * Z + m / 8
-    vn = w * E_state + 8 * NC * Z
-    return cn, vn
-
-
-def roofline_entry(kr, F, where):
+def roofline_entry(kr, F, where, fp16=False):
     """The roofline object of the dominant kernel (the check pass) from the
-    per-kernel events of kernel_roofline."""
+    per-kernel events of kernel_roofline: its HBM roofline, and beside it the
+    instruction-issue ceiling from the counters; `bound` names the ceiling
+    that allows the longer minimum time (HBM bytes at 8 TB/s, or issue slots
+    at the VALU issue peak)."""
     dom = max(kr, key=lambda k: kr[k]["share"])
-    return {"bound": "hbm", "kernel": dom, "achieved": round(kr[dom]["achieved_GBs"], 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(kr[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(f"{dom}_F{F}"),
-            "algorithmic_bytes": kr[dom]["bytes_per_launch"], "avg_ms": kr[dom]["avg_ms"],
-            "working_set": where, "kernels": kr}
+    k = kr[dom]
+    hbm_ms = k["bytes_per_launch"] / (HBM_PEAK_GBS * 1e9) * 1e3
+    iss = issue_ceiling(f"{dom}_{'fp16' if fp16 else 'fp32'}", F, k["avg_ms"])
+    ent = {"bound": "hbm", "kernel": dom, "achieved": round(k["achieved_GBs"], 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(k["achieved_GBs"] / HBM_PEAK_GBS, 4),
+           "traffic": None if fp16 else measured_traffic(f"{dom}_F{F}"),
+           "algorithmic_bytes": k["bytes_per_launch"], "avg_ms": k["avg_ms"],
+           "hbm_min_ms": hbm_ms, "issue": iss, "working_set": where, "kernels": kr}
+    if iss is not None and iss["min_ms"] > hbm_ms:
+        # instruction issue allows less than HBM does: report against it
+        ent.update({"bound": "alu", "achieved": round(iss["issue_slots"] / (k["avg_ms"] * 1e-3) / 1e9, 1),
+                    "peak": VALU_ISSUE_PEAK / 1e9, "unit": "G wave64 issue slots/s",
+                    "frac": round(iss["frac"], 4), "hbm_frac": round(k["achieved_GBs"] / HBM_PEAK_GBS, 4)})
+    return ent
 
 
 def cpu_model() -> str:
@@ -624,6 +662,9 @@ def main():
         res["roofline"] = roofline_entry(kr, F, "cache-resident: about 131 MB of decode state and "
                                                 "inputs for 8 frames, inside the 256 MB Infinity "
                                                 "Cache")
+        if "fp16" in res:
+            kr16 = kernel_roofline(torch, code, dQ, ds, T, steps_r, F, info, fp16=True)
+            res["fp16"]["roofline"] = roofline_entry(kr16, F, "cache-resident", fp16=True)
         print("[bench] roofline done", file=sys.stderr, flush=True)
 
     if not args.no_hbm_point:
