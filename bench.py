@@ -39,19 +39,19 @@ PAPER_KRAW_MBPS = 1.72       # GTX 1080, q=21 QC code, Table II (context only)
 # only for the kernel sources it was taken on; any change to them makes the
 # fingerprint differ and the figure is reported as null.
 KERNEL_SOURCES = ("internal.h", "passes.h", "decoder.hip")
-MEASURED_SOURCES = "6226262a246d4d5b"
+MEASURED_SOURCES = "bd54638370136c33"
 MEASURED_TRAFFIC = {
-    "check_pass_F8": {"fetch_kib": 50792.4, "write_kib": 64746.9, "fetch_scale": 2.0,
+    "check_pass_F8": {"fetch_kib": 51080.9, "write_kib": 66047.6, "fetch_scale": 2.0,
                       "write_scale": 1.0},
-    "check_pass_F32": {"fetch_kib": 202958.8, "write_kib": 258998.1, "fetch_scale": 2.0,
+    "check_pass_F32": {"fetch_kib": 205991.2, "write_kib": 264354.5, "fetch_scale": 2.0,
                        "write_scale": 1.0},
 }
 # Instruction counts of the steady check pass per frame (rocprofv3 --pmc
 # SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32, SQ_INSTS_SALU per 8-frame dispatch,
 # divided by 8): wave64 instructions, transcendentals included in VALU.
 MEASURED_ISSUE = {
-    "check_pass_fp32": {"valu": 7.948e6 / 8, "trans": 0.802e6 / 8, "salu": 7.210e6 / 8},
-    "check_pass_fp16": {"valu": 8.671e6 / 8, "trans": 0.802e6 / 8, "salu": 7.210e6 / 8},
+    "check_pass_fp32": {"valu": 7.138e6 / 8, "trans": 0.800e6 / 8, "salu": 2.950e6 / 8},
+    "check_pass_fp16": {"valu": 7.783e6 / 8, "trans": 0.800e6 / 8, "salu": 3.020e6 / 8},
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, each issuing one wave64 VALU
 # instruction every 4 cycles, at 2.4 GHz = 614.4 G wave-instructions/s.  A
@@ -186,13 +186,16 @@ def kernel_roofline(torch, code, dQ, ds, T, steps, F, info, fp16=False):
     E_d1 = info["deg1_cols"] * Z
     NC = info["core_cols"]
     m = info["m"]
-    # algorithmic bytes per frame (w-byte messages): each stored message read
-    # once and written once per check pass (written only at t = 1), the
-    # degree-1 inputs and the packed syndrome bits; the variable pass reads
-    # every message once, the core channel LLRs, and writes the core totals.
-    cn_bytes = np.array([(w if t == 1 else 2 * w) * E_state + 4 * E_d1 + m / 8
+    P = info["owner_groups"] * Z      # owner-group partial sums
+    E_other = E_state - info["owned_edges"]
+    # algorithmic bytes per frame (w-byte messages): the check pass reads and
+    # writes each stored message once (writes only at t = 1), reads the
+    # degree-1 inputs and the packed syndrome bits, and writes the partial
+    # sums; the variable pass reads the messages outside owner blocks, the
+    # partial sums and the core channel LLRs, and writes the core totals.
+    cn_bytes = np.array([(w if t == 1 else 2 * w) * E_state + 4 * E_d1 + m / 8 + 4 * P
                          for t in range(1, T + 1)])
-    vn_bytes = np.full(T, w * E_state + 8 * NC * Z, dtype=np.float64)
+    vn_bytes = np.full(T, w * E_other + 4 * P + 8 * NC * Z, dtype=np.float64)
     active_cn = np.array([np.sum(iters >= t - 1) for t in range(1, T + 1)])
     active_vn = np.array([np.sum(iters >= t) for t in range(1, T + 1)])
     cn_gbs = float(np.sum(cn_bytes * active_cn) / (np.sum(cn_ms) * 1e-3) / 1e9)

@@ -143,6 +143,36 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
             col_ref[c] = -1;
         }
     }
+    // Owner of each row of the t-domain class (two core blocks and one
+    // degree-1 block): of its two core columns, the one that owns fewer rows
+    // so far (ties: the lower column).  The row's checks are relabelled so
+    // the owner block gets shift 0: every shift of the row drops by the owner
+    // block's shift (mod Z).
+    std::vector<int32_t> row_rot(mb, 0), row_owner(mb, -1);
+    {
+        std::vector<int32_t> owned(nb, 0);
+        for (int r = 0; r < mb; ++r) {
+            int ncore = 0, nd1 = 0, cc[2] = {-1, -1};
+            for (int c = 0; c < nb; ++c) {
+                if (base[(size_t)r * nb + c] < 0) continue;
+                if (col_kind[c] == ldpc::COL_CORE) {
+                    if (ncore < 2) cc[ncore] = c;
+                    ++ncore;
+                } else {
+                    ++nd1;
+                }
+            }
+            if (ncore != 2 || nd1 != 1) continue;
+            const int o = owned[cc[1]] < owned[cc[0]] ? cc[1] : cc[0];
+            owned[o]++;
+            row_owner[r] = o;
+            row_rot[r] = base[(size_t)r * nb + o];
+        }
+    }
+    auto shift_of = [&](int r, int c) {
+        const int32_t s = base[(size_t)r * nb + c] - row_rot[r];
+        return s < 0 ? s + Z : s;
+    };
     // blocks in row-major order; state blocks numbered in that order
     std::vector<int32_t> row_first(mb), row_deg(mb);
     std::vector<int32_t> blk_shift, blk_kind, blk_ref, blk_col, blk_core;
@@ -153,16 +183,18 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     for (int r = 0; r < mb; ++r) {
         row_first[r] = (int32_t)blk_shift.size();
         int d = 0;
-        // within a row: blocks of stored columns first, then degree-1 blocks,
-        // each group in increasing column order
+        // within a row: blocks of stored columns first (the owner block
+        // leading), then degree-1 blocks, each group in increasing column order
         std::vector<int> cols;
+        if (row_owner[r] >= 0) cols.push_back(row_owner[r]);
         for (int c = 0; c < nb; ++c)
-            if (base[(size_t)r * nb + c] >= 0 && col_kind[c] == ldpc::COL_CORE) cols.push_back(c);
+            if (base[(size_t)r * nb + c] >= 0 && col_kind[c] == ldpc::COL_CORE && c != row_owner[r])
+                cols.push_back(c);
         row_ns[r] = (int32_t)cols.size();
         for (int c = 0; c < nb; ++c)
             if (base[(size_t)r * nb + c] >= 0 && col_kind[c] != ldpc::COL_CORE) cols.push_back(c);
         for (int c : cols) {
-            const int32_t s = base[(size_t)r * nb + c];
+            const int32_t s = shift_of(r, c);
             ++d;
             blk_shift.push_back(s);
             blk_col.push_back(c);
@@ -284,15 +316,68 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         dd[18] = cls_of(r);
     }
     const size_t o_rd = put(row_desc);
-    // per core column: (message offset, shift) of its blocks at a fixed stride
+    // owner groups: per core column, its owned rows in increasing row order,
+    // kGroupRows at a time
+    std::vector<int32_t> grp_hdr, grp_desc;
+    std::vector<int32_t> core_own(NC, 0), core_ngrp(NC, 0), core_grp0(NC, 0);
+    // per core column: its blocks in summation order (owned blocks group by
+    // group, then the others), as indices into core_state / core_shift
+    std::vector<std::vector<int32_t>> core_order(NC);
+    int n_groups = 0;
+    for (int k = 0; k < NC; ++k) {
+        std::vector<int32_t> own_rows;
+        for (int r = 0; r < mb; ++r)
+            if (row_owner[r] == core_col[k]) own_rows.push_back(r);
+        core_own[k] = (int32_t)own_rows.size();
+        core_grp0[k] = n_groups;
+        for (size_t i0 = 0; i0 < own_rows.size(); i0 += ldpc::kGroupRows) {
+            const int cnt = (int)std::min<size_t>(ldpc::kGroupRows, own_rows.size() - i0);
+            grp_hdr.insert(grp_hdr.end(), {k * Zt, cnt, 0, 0});
+            for (int i = 0; i < ldpc::kGroupRows; ++i) {
+                int32_t dd[ldpc::kGroupDescWords] = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (i < cnt) {
+                    const int r = own_rows[i0 + i];
+                    const int b0 = row_first[r], b1 = b0 + 1, b2 = b0 + 2;
+                    dd[0] = blk_ref[b0] * Zp;
+                    dd[1] = blk_ref[b1] * Zp;
+                    dd[2] = blk_core[b1] * Zt + blk_shift[b1];
+                    dd[3] = blk_ref[b2] * Zp;
+                    dd[4] = blk_ref[b2] * W;
+                    dd[5] = r * W;
+                    dd[6] = blk_col[b2] * Z;
+                    dd[7] = blk_shift[b2];
+                }
+                grp_desc.insert(grp_desc.end(), dd, dd + ldpc::kGroupDescWords);
+            }
+            ++n_groups;
+        }
+        core_ngrp[k] = n_groups - core_grp0[k];
+        // summation order: owned blocks (own_rows order), then the others
+        std::vector<int32_t> &ord = core_order[k];
+        for (int r : own_rows)
+            for (int i = 0; i < core_deg[k]; ++i)
+                if (st_row[core_state[core_first[k] + i]] == r) ord.push_back(core_first[k] + i);
+        for (int i = 0; i < core_deg[k]; ++i)
+            if (row_owner[st_row[core_state[core_first[k] + i]]] != core_col[k])
+                ord.push_back(core_first[k] + i);
+    }
+    int max_half_terms = 1;
+    for (int k = 0; k < NC; ++k) {
+        const int terms = core_ngrp[k] + core_deg[k] - core_own[k];
+        max_half_terms = std::max(max_half_terms, (terms + 1) / 2);
+    }
+    const size_t o_gh = put(grp_hdr), o_gd = put(grp_desc), o_rot = put(row_rot);
+    const size_t o_cown = put(core_own), o_cng = put(core_ngrp), o_cg0 = put(core_grp0);
+    // per core column: (message offset, shift) of its blocks at a fixed
+    // stride, in summation order
     int max_cd = 1;
     for (int k = 0; k < NC; ++k) max_cd = std::max(max_cd, core_deg[k]);
     const int tab_stride = 2 * max_cd;
     std::vector<int32_t> core_tab((size_t)std::max(NC, 1) * tab_stride, 0);
     for (int k = 0; k < NC; ++k)
         for (int i = 0; i < core_deg[k]; ++i) {
-            core_tab[(size_t)k * tab_stride + 2 * i] = core_state[core_first[k] + i] * Zp;
-            core_tab[(size_t)k * tab_stride + 2 * i + 1] = core_shift[core_first[k] + i];
+            core_tab[(size_t)k * tab_stride + 2 * i] = core_state[core_order[k][i]] * Zp;
+            core_tab[(size_t)k * tab_stride + 2 * i + 1] = core_shift[core_order[k][i]];
         }
     const size_t o_ct = put(core_tab);
     // the same tables in the frame-resident schedule's LDS layout (stride Z)
@@ -321,8 +406,8 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     std::vector<int32_t> res_core((size_t)std::max(NC, 1) * res_stride + res_batch, 0);
     for (int k = 0; k < NC; ++k)
         for (int i = 0; i < core_deg[k]; ++i) {
-            res_core[(size_t)k * res_stride + 2 * i] = core_state[core_first[k] + i] * Z;
-            res_core[(size_t)k * res_stride + 2 * i + 1] = core_shift[core_first[k] + i];
+            res_core[(size_t)k * res_stride + 2 * i] = core_state[core_order[k][i]] * Z;
+            res_core[(size_t)k * res_stride + 2 * i + 1] = core_shift[core_order[k][i]];
         }
     const size_t o_resc = put(res_core);
     // check-phase units in class order (only where a frame could fit in LDS:
@@ -409,6 +494,15 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     d.d1_shift = T + o_d1s;
     d.d1_col = T + o_d1c;
     d.d1_tdom = T + o_d1t;
+    d.row_rot = T + o_rot;
+    d.n_groups = n_groups;
+    d.n_tdom = cls_end[ldpc::kTdomClass] - cls_end[ldpc::kTdomClass - 1];
+    d.grp_hdr = T + o_gh;
+    d.grp_desc = T + o_gd;
+    d.core_own = T + o_cown;
+    d.core_ngrp = T + o_cng;
+    d.core_grp0 = T + o_cg0;
+    d.max_half_terms = max_half_terms;
 
     ldpc_code_info_t &I = code->info;
     I.n = d.n;
@@ -423,6 +517,10 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
     I.deg1_cols = ND1;
     I.deg0_cols = nb - NC - ND1;
     I.max_row_degree = maxdeg;
+    int64_t owned = 0;
+    for (int k = 0; k < NC; ++k) owned += core_own[k];
+    I.owned_edges = owned * Z;
+    I.owner_groups = n_groups;
     *out = code;
     return LDPC_OK;
 }

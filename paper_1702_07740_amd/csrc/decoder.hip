@@ -64,6 +64,31 @@ __global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, FastDi
     check_pass_body<Msg, false, MODE, CPT>(c, A, tiles, rows, frames);
 }
 
+// The check pass of a code with owner groups: per frame, the (group, tile)
+// items of the t-domain rows come first, then the (row, tile) items of the
+// other common rows (row-list positions outside the t-domain class's range).
+template <typename Msg, int MODE, int CPT>
+__global__ __launch_bounds__(kBlock) void check_pass_grouped(CodeDev c, CnArgs A, FastDiv per_frame,
+                                                             FastDiv gtiles, FastDiv rtiles,
+                                                             unsigned group_items,
+                                                             unsigned frames) {
+    const unsigned n = per_frame.d * frames;
+    const unsigned i = xcd_item(blockIdx.x, n);
+    if (i >= n) return;
+    const unsigned f = fdiv(i, per_frame);
+    const unsigned r = i - f * per_frame.d;
+    if (r < group_items) {
+        const unsigned g = fdiv(r, gtiles);
+        group_work<MODE, Msg>(c, A, (int)f, (int)g, r - g * gtiles.d);
+    } else {
+        const unsigned r2 = r - group_items;
+        const unsigned y0 = fdiv(r2, rtiles);
+        const int lo = c.cls_end[kTdomClass - 1];
+        const int y = (int)y0 < lo ? (int)y0 : (int)y0 + c.n_tdom;
+        check_work<Msg, false, MODE, CPT>(c, A, (int)f, y, r2 - y0 * rtiles.d);
+    }
+}
+
 template <typename Msg, int MODE, int CPT>
 __global__ __launch_bounds__(kBlock) void check_pass_large(CodeDev c, CnArgs A, FastDiv tiles,
                                                            FastDiv rows, unsigned frames) {
@@ -88,6 +113,41 @@ void launch_check_pass(const CodeDev &c, const CnArgs &a, int F, int cpt, hipStr
                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
     const bool both = c.n_small > 0 && c.n_large > 0;
     const unsigned fr = (unsigned)F;
+    if constexpr (base_mode(MODE) != kVoteOnly) {
+        if (c.n_groups > 0) {
+            // owner groups (256 positions per item) and the other common rows
+            if constexpr (with_post(MODE)) cpt = kDefaultChecksPerThread;
+            const unsigned gt = (unsigned)((c.Z + kBlock - 1) / kBlock);
+            const unsigned rt = check_tiles(c.Z, cpt);
+            const unsigned gi = gt * (unsigned)c.n_groups;
+            const unsigned per = gi + rt * (unsigned)(c.n_small - c.n_tdom);
+            const dim3 g(xcd_grid(per * fr));
+            const FastDiv dp = fast_div(per), dg = fast_div(gt), dr = fast_div(rt);
+            hipEvent_t e1 = both ? nullptr : stop;
+            if constexpr (with_post(MODE)) {
+                launch_timed(check_pass_grouped<Msg, MODE, kDefaultChecksPerThread>, g, st, start,
+                             e1, c, a, dp, dg, dr, gi, fr);
+            } else {
+                if (cpt == 1)
+                    launch_timed(check_pass_grouped<Msg, MODE, 1>, g, st, start, e1, c, a, dp, dg,
+                                 dr, gi, fr);
+                else if (cpt == 2)
+                    launch_timed(check_pass_grouped<Msg, MODE, 2>, g, st, start, e1, c, a, dp, dg,
+                                 dr, gi, fr);
+                else
+                    launch_timed(check_pass_grouped<Msg, MODE, 4>, g, st, start, e1, c, a, dp, dg,
+                                 dr, gi, fr);
+            }
+            if (c.n_large > 0) {
+                const unsigned tl = check_tiles(c.Z, kDefaultChecksPerThread),
+                               rows = (unsigned)c.n_large;
+                launch_timed(check_pass_large<Msg, MODE, kDefaultChecksPerThread>,
+                             dim3(xcd_grid(tl * rows * fr)), st, nullptr, stop, c, a,
+                             fast_div(tl), fast_div(rows), fr);
+            }
+            return;
+        }
+    }
     if (c.n_small > 0) {
         if constexpr (with_post(MODE)) cpt = kDefaultChecksPerThread;
         const unsigned tl = check_tiles(c.Z, cpt), rows = (unsigned)c.n_small;
@@ -124,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void variable_pass(CodeDev c, VnArgs A, Fas
     const unsigned tile = i - i1 * tiles.d;
     const unsigned f = fdiv(i1, cols);
     if (A.fail[(size_t)(A.t - 1) * A.F + f] == 0) return;
-    variable_work<U, Msg, vn_vpt<Msg>()>(c, A, (int)f, (int)(i1 - f * cols.d), tile);
+    variable_work<U, Msg, vn_vpt<Msg>(), true>(c, A, (int)f, (int)(i1 - f * cols.d), tile);
 }
 
 template <typename Msg>
@@ -134,7 +194,7 @@ void launch_variable_pass(const CodeDev &c, const VnArgs &v, int F, hipStream_t 
     const dim3 g(xcd_grid(tl * (unsigned)c.NC * (unsigned)F));
     const FastDiv dt = fast_div(tl), dc = fast_div((unsigned)c.NC);
     const unsigned fr = (unsigned)F;
-    switch (variable_group(c.max_core_deg)) {
+    switch (variable_group(2 * c.max_half_terms)) {
         case 4: launch_timed(variable_pass<4, Msg>, g, st, start, stop, c, v, dt, dc, fr); break;
         case 8: launch_timed(variable_pass<8, Msg>, g, st, start, stop, c, v, dt, dc, fr); break;
         case 13: launch_timed(variable_pass<13, Msg>, g, st, start, stop, c, v, dt, dc, fr); break;
@@ -176,13 +236,15 @@ __global__ __launch_bounds__(kBlock) void finalize(CodeDev c, FinArgs A) {
 __global__ __launch_bounds__(kBlock) void syndrome_kernel(CodeDev c, const uint8_t *bits,
                                                           uint8_t *syn) {
     const int f = blockIdx.z, r = blockIdx.y;
-    const int a = blockIdx.x * kBlock + threadIdx.x;
+    const int a = blockIdx.x * kBlock + threadIdx.x;  // check index in the code as given
     if (a >= c.Z) return;
     const uint8_t *x = bits + (size_t)f * c.n;
     const int b0 = c.row_first[r], d = c.row_deg[r];
+    int ar = a + c.row_rot[r];  // the same check in the relabelled tables
+    ar -= (ar >= c.Z) ? c.Z : 0;
     int p = 0;
     for (int k = 0; k < d; ++k) {
-        int j = a + c.blk_shift[b0 + k];
+        int j = ar + c.blk_shift[b0 + k];
         j -= (j >= c.Z) ? c.Z : 0;
         p ^= x[(size_t)c.blk_col[b0 + k] * c.Z + j] & 1;
     }
@@ -235,6 +297,8 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     a.d1_frame = L.d1bits_frame;
     a.syn_frame = L.synbits_frame;
     a.psi_frame = L.psi_frame;
+    a.part = reinterpret_cast<float *>(ws + L.part);
+    a.part_frame = L.part_frame;
     a.F = F;
 
     VnArgs v{};
@@ -244,6 +308,8 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
     v.fail = fail;
     v.msg_frame = L.msg_frame;
     v.tot_frame = L.tot_frame;
+    v.part = reinterpret_cast<const float *>(ws + L.part);
+    v.part_frame = L.part_frame;
     v.F = F;
 
     for (int t = 1; t <= T; ++t) {
@@ -331,6 +397,9 @@ WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr)
     off = align256(off + (size_t)(T + 1) * F * 4);
     L.d1post = off;
     if (want_llr) off = align256(off + 2 * (size_t)F * L.psi_frame * 4);
+    L.part_frame = (size_t)c.n_groups * c.Zp;
+    L.part = off;
+    off = align256(off + (size_t)F * L.part_frame * 4);
     L.total = off;
     return L;
 }

@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void engine_variable_pass(const SlotDesc *s
     CodeDev c = S.c;
     c.core_tab = H.tab;
     c.core_tab_stride = H.stride;
-    variable_work<U, Msg, 1>(c, V, f, k, tile);
+    variable_work<U, Msg, 1, false>(c, V, f, k, tile);
 }
 
 template <typename Msg>

@@ -35,6 +35,22 @@ constexpr int kTdomClass = 4;
 // Words of a common row's descriptor (see CodeDev::row_desc).
 constexpr int kRowDescWords = 20;
 
+// Owner groups.  Every row of the t-domain class has two core blocks; one of
+// them, chosen so that the core columns own about equally many rows, is the
+// row's owner block.  The row's checks are relabelled (check a becomes
+// (a + s) mod Z, s the owner block's shift), so the owner block has shift 0
+// and the row's check a meets the owner column at position a.  Rows with the
+// same owner column, kGroupRows at a time in increasing row order, form a
+// group; a group's checks at one position all feed the same core variable,
+// so the check pass adds their messages to that variable into one partial
+// sum per group, and the variable pass reads the partial instead of the
+// group's messages.
+// Measured on the rate-0.02 template (24 owned rows per core column) at
+// Z = 6667: groups of 24 rows beat 4, 6, 8, 12 and 16 (fewer partials for the
+// variable pass, and the owner total read once for more rows).
+constexpr int kGroupRows = 24;
+constexpr int kGroupDescWords = 8;
+
 // Words of a row's descriptor for the frame-resident schedule (see
 // CodeDev::res_desc), and the blocks its variable phase reads per batch.
 constexpr int kResDescWords = 24;
@@ -125,11 +141,36 @@ struct CodeDev {
     // blocks), updated in the t-domain, so its input is +-e^{-|Q|} rather than
     // +-Phi(|Q|)
     const int32_t *d1_tdom;
+    // per base row r: the relabelling of its checks: check a of the code as
+    // given is check (a + row_rot[r]) mod Z of the tables above (0 for rows
+    // without an owner)
+    const int32_t *row_rot;
+    // owner groups: per group g, grp_hdr[4 g ..] = owner column's totals
+    // offset (core * Zt), row count, 0, 0; per row i of the group,
+    // kGroupDescWords words at grp_desc[(g kGroupRows + i) kGroupDescWords]:
+    //   0 owner block's message offset (state index * Zp), 1 the other core
+    //   block's message offset, 2 the other block's totals offset plus shift
+    //   (core * Zt + s), 3 Psi offset (degree-1 index * Zp), 4 decision-word
+    //   offset (degree-1 index * W), 5 syndrome-word offset (r * W),
+    //   6 degree-1 column's LLR offset (column * Z), 7 degree-1 shift
+    int32_t n_groups, n_tdom;  // groups; rows of the t-domain class
+    const int32_t *grp_hdr, *grp_desc;
+    // per core column k: the first core_own[k] entries of core_tab and
+    // res_core are its owned blocks, group by group (kGroupRows per group,
+    // rows increasing), the rest its other blocks (rows increasing);
+    // core_ngrp[k] groups, numbered from core_grp0[k].  The column's total is
+    //   L = (Q log2(e) + S0) + S1,
+    // over the terms P_0 .. P_{G-1} (group partials, each summed from +0 in
+    // row order) followed by the other blocks' messages: S0 sums the first
+    // ceil(terms / 2) terms from +0, S1 the rest.
+    const int32_t *core_own, *core_ngrp, *core_grp0;
+    int32_t max_half_terms;  // largest ceil(terms / 2) over the core columns
 };
 
 // Byte offsets of the decode workspace for F frames and T iterations.
 struct WorkLayout {
-    size_t msg, tot, psi, d1bits, synbits, fail, d1post, total;
+    size_t msg, tot, psi, d1bits, synbits, fail, d1post, part, total;
+    size_t part_frame;     // floats per frame (group partials, n_groups * Zp)
     size_t msg_frame;      // elements per frame
     size_t tot_frame;      // floats per frame
     size_t psi_frame;      // floats per frame (degree-1 inputs; also posteriors)

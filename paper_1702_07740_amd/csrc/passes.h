@@ -119,6 +119,12 @@ template <> __device__ __forceinline__ void msg_store<float>(float *p, float v) 
 template <> __device__ __forceinline__ void msg_store<_Float16>(_Float16 *p, float v) {
     *p = static_cast<_Float16>(v);
 }
+// The value a message reads back as after msg_store.
+template <typename Msg> __device__ __forceinline__ float msg_round(float v);
+template <> __device__ __forceinline__ float msg_round<float>(float v) { return v; }
+template <> __device__ __forceinline__ float msg_round<_Float16>(float v) {
+    return static_cast<float>(static_cast<_Float16>(v));
+}
 
 __device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
 
@@ -145,7 +151,8 @@ struct CnArgs {
     const uint64_t *synbits;   // [F][mb][W]
     int32_t *fail;             // [T+1][F]
     float *d1post;             // [F][ND1][Z] degree-1 posteriors of iteration t, or null
-    size_t msg_frame, tot_frame, d1_frame, syn_frame, psi_frame;
+    float *part;               // [F][n_groups][Zp] owner-group partial sums (grouped launches)
+    size_t msg_frame, tot_frame, d1_frame, syn_frame, psi_frame, part_frame;
     int F, t;
     int vote;                  // 1: record the check of iteration t-1 (t when vote-only)
     int d1_from_llr;           // vote-only at t = 0: decisions come from the channel signs
@@ -819,12 +826,160 @@ __device__ __forceinline__ void check_work_by_desc(const CodeDev &c, const CnArg
 #undef LDPC_CLASS
 }
 
+// Workgroup-uniform pointers of one (frame, owner group).
+template <typename Msg>
+struct GroupView {
+    const int32_t *desc;   // the group's row descriptors
+    const float *tot, *psi, *llr;
+    Msg *msg;
+    const uint64_t *syn, *dprev;
+    uint64_t *dcur;
+    float *post;
+    unsigned Z, Wm1;
+};
+
+// RB rows k0 .. k0 + RB - 1 of an owner group at position p (check p of each
+// row, variable p of the owner column, whose total tv is read once for the
+// group); w = the wave's word.  The update of each row is that of
+// tdom_chunks, term for term; the new message to the owner column is added
+// to psum as it will read back from storage.  All loads of the RB rows are
+// issued before the first wait.
+template <int MODE, typename Msg, int RB, bool FULL>
+__device__ __forceinline__ void group_batch(const GroupView<Msg> &G, int k0, float tv, unsigned p,
+                                            unsigned w, float &psum, uint32_t &bad,
+                                            const PhiConsts &PK) {
+    static_assert(base_mode(MODE) != kVoteOnly, "vote-only launches take the row kernel");
+    typedef const __attribute__((address_space(4))) int32_t ConstI32;
+    ConstI32 *dp = (ConstI32 *)(G.desc + (size_t)k0 * kGroupDescWords);
+    const unsigned lane = threadIdx.x & 63u;
+    const bool valid = FULL || p < G.Z;
+    unsigned d[RB][kGroupDescWords];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < kGroupDescWords; ++j) d[i][j] = (unsigned)dp[i * kGroupDescWords + j];
+    uint64_t sw[RB], dw[RB];
+    float lt[RB], mo0[RB], mo1[RB], ps[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        sw[i] = uniform_word(G.syn + d[i][5] + w);
+        dw[i] = (base_mode(MODE) != kFirst) ? uniform_word(G.dprev + d[i][4] + w) : 0ull;
+        lt[i] = at(G.tot + d[i][2], p);
+        mo0[i] = (base_mode(MODE) == kSteady) ? msg_load<Msg>(&at(G.msg + d[i][0], p)) : 0.0f;
+        mo1[i] = (base_mode(MODE) == kSteady) ? msg_load<Msg>(&at(G.msg + d[i][1], p)) : 0.0f;
+        ps[i] = at(G.psi + d[i][3], p);
+    }
+    uint64_t dbits[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const uint32_t syn = lane_bit(sw[i]) ? kSignBit : 0u;
+        const uint32_t s2 = __float_as_uint(ps[i]) & kSignBit;  // sign of Q (never -0)
+        const uint32_t d1 = (base_mode(MODE) == kFirst) ? s2 : (lane_bit(dw[i]) ? kSignBit : 0u);
+        const uint32_t vpar = syn ^ neg_bit(tv) ^ neg_bit(lt[i]) ^ d1;
+        bad |= valid ? vpar : 0u;
+        const float x0 = tv - mo0[i], x1 = lt[i] - mo1[i];
+        const uint32_t s0 = neg_bit(x0), s1 = neg_bit(x1);
+        float mag0, mag1, t1, t2;
+        bool q_wins;
+        tdom_check3(x0, x1, fabsf(ps[i]), PK, mag0, mag1, q_wins, t1, t2);
+        const float m0 = __uint_as_float(__float_as_uint(mag0) | (syn ^ s1 ^ s2));
+        const float m1 = __uint_as_float(__float_as_uint(mag1) | (syn ^ s0 ^ s2));
+        if (valid) {
+            msg_store<Msg>(&at(G.msg + d[i][0], p), m0);
+            msg_store<Msg>(&at(G.msg + d[i][1], p), m1);
+        }
+        psum += msg_round<Msg>(m0);
+        const uint32_t par = syn ^ s0 ^ s1 ^ s2;
+        const uint32_t dd = s2 ^ (q_wins ? 0u : par);
+        dbits[i] = wave_ballot(valid && dd != 0u);
+        if constexpr (with_post(MODE)) {
+            if (valid) {
+                unsigned j = p + d[i][7];
+                j -= (j >= G.Z) ? G.Z : 0u;
+                const float mp = tdom_mag(t1, t2) * kLn2;
+                at(G.post + d[i][3], p) = at(G.llr + d[i][6], j) + ((syn ^ s0 ^ s1) ? -mp : mp);
+            }
+        }
+    }
+    // lane i < RB stores row i's decision word
+    if (lane < (unsigned)RB) {
+        uint64_t v = dbits[0];
+        unsigned off = d[0][4];
+#pragma unroll
+        for (int i = 1; i < RB; ++i) {
+            v = (lane == (unsigned)i) ? dbits[i] : v;
+            off = (lane == (unsigned)i) ? d[i][4] : off;
+        }
+        if (FULL || w <= G.Wm1) at(G.dcur + off, w) = v;
+    }
+}
+
+// Rows of an owner group whose loads are in flight together (measured: 4
+// beats 2, 3, 6 and 8 at 24 rows per group).
+constexpr int kGroupBatch = 4;
+
+template <int MODE, typename Msg, bool FULL>
+__device__ __forceinline__ void group_rows(const GroupView<Msg> &G, int nrows, float tv, unsigned p,
+                                           unsigned w, float &psum, uint32_t &bad,
+                                           const PhiConsts &PK) {
+    int k = 0;
+    for (; k + kGroupBatch <= nrows; k += kGroupBatch)
+        group_batch<MODE, Msg, kGroupBatch, FULL>(G, k, tv, p, w, psum, bad, PK);
+    for (; k < nrows; ++k) group_batch<MODE, Msg, 1, FULL>(G, k, tv, p, w, psum, bad, PK);
+}
+
+// Check update of one (frame, owner group g, 256 positions) work item: every
+// row of the group at positions p = tile 256 + thread (Alg. 1 Step 2 and the
+// Step 4 check of iteration t-1, as for the rows' own work items), plus the
+// group's partial sum of the new messages to the owner column, written to
+// part[f][g][p].  Padding lanes (p >= Z) read in-bounds slack and store
+// nothing, as in tdom_chunks.
+template <int MODE, typename Msg>
+__device__ __forceinline__ void group_work(const CodeDev &c, const CnArgs &A, int f, int g,
+                                           unsigned tile) {
+    const PhiConsts PK = phi_consts();
+    int32_t *flag = vote_flag<MODE>(A, f);
+    const int32_t prev = uniform_i32(A.fail + (size_t)max(A.skip_after, 0) * A.F + f);
+    const int32_t seen = uniform_i32(flag);
+    const int32_t own = uniform_i32(c.grp_hdr + 4 * g);
+    const int32_t nrows = uniform_i32(c.grp_hdr + 4 * g + 1);
+    const bool skip = (A.skip_after >= 0) & (prev == 0);
+    if (skip | (nrows <= 0)) return;
+    GroupView<Msg> G;
+    G.desc = c.grp_desc + (size_t)g * kGroupRows * kGroupDescWords;
+    G.tot = A.tot + (size_t)f * A.tot_frame;
+    G.psi = A.psi + (size_t)f * A.psi_frame;
+    G.llr = A.llr + (size_t)f * c.n;
+    G.msg = reinterpret_cast<Msg *>(A.msg) + (size_t)f * A.msg_frame;
+    G.syn = A.synbits + (size_t)f * A.syn_frame;
+    G.dprev = A.d1_prev + (size_t)f * A.d1_frame;
+    G.dcur = A.d1_cur + (size_t)f * A.d1_frame;
+    G.post = A.d1post ? A.d1post + (size_t)f * A.psi_frame : nullptr;
+    G.Z = (unsigned)c.Z;
+    G.Wm1 = (unsigned)c.W - 1;
+    const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned p = tile * kBlock + threadIdx.x;
+    const unsigned w = tile * 4u + wave;
+    const float tv = at(G.tot + (unsigned)own, p);
+    float psum = 0.0f;
+    uint32_t bad = 0;
+    if ((tile + 1) * kBlock <= G.Z) {
+        group_rows<MODE, Msg, true>(G, nrows, tv, p, w, psum, bad, PK);
+        at(A.part + (size_t)f * A.part_frame + (size_t)g * c.Zp, p) = psum;
+    } else {
+        group_rows<MODE, Msg, false>(G, nrows, tv, p, w, psum, bad, PK);
+        if (p < G.Z) at(A.part + (size_t)f * A.part_frame + (size_t)g * c.Zp, p) = psum;
+    }
+    if (A.vote) vote_store(flag, seen, bad != 0u);
+}
+
 struct VnArgs {
     const float *llr;
     const void *msg;
+    const float *part;         // owner-group partials, or null: rebuilt from the messages
     float *tot;
     const int32_t *fail;
-    size_t msg_frame, tot_frame;
+    size_t msg_frame, tot_frame, part_frame;
     int F, t;
 };
 
@@ -835,17 +990,18 @@ struct VnArgs {
 // whole column as a chain of dependent batches.
 constexpr int kVnGroups = 2;  // measured: 2 groups of 128 variables beat 1 x 256 and 4 x 64
 constexpr int kVnLanes = kBlock / kVnGroups;
-// Variables per thread (VPT): the single-call decoder takes 2 for
-// half-precision messages, whose loads are latency-bound at one variable per
-// thread, else 1.
-template <typename Msg> constexpr int vn_vpt() { return sizeof(Msg) == 2 ? 2 : 1; }
+// Variables per thread (VPT) of the single-call decoder: 2, so that every
+// thread has a whole row group's loads for two variables in flight (measured:
+// the variable pass of the rate-0.02 template at Z = 6667 takes 8.2 us for 8
+// frames with 2, 9.4 us with 1).
+template <typename Msg> constexpr int vn_vpt() { return 2; }
 inline unsigned variable_tiles(int Z, int vpt) {
     const int v = kVnLanes * vpt;
     return (unsigned)((Z + v - 1) / v);
 }
 
-// Loads per row group and variable issued together: the group size
-// ceil(max_deg / groups), rounded up to an instantiated width (a longer group
+// Loads per row group and variable issued together: ceil(n / groups) for a
+// column of n terms, rounded up to an instantiated width (a longer group
 // takes several batches).
 inline int variable_group(int max_deg) {
     const int g = ((max_deg > 0 ? max_deg : 1) + kVnGroups - 1) / kVnGroups;
@@ -866,15 +1022,20 @@ __device__ __forceinline__ float core_total(float q, const float (&part)[kVnGrou
 }
 
 // Step 3 for the core columns: L_v = Q_v + sum of the column's messages (in
-// base 2: Q_v log2(e) plus the base-2 messages).  Row group g (blocks
-// [g p, (g + 1) p), p = ceil(deg / groups)) is summed in increasing row order;
-// the group sums meet in LDS and L = (Q + S0) + S1 ..., a fixed order.
+// base 2: Q_v log2(e) plus the base-2 messages), in the column's fixed
+// summation order: the terms are the owner-group partials P_0 .. P_{G-1}
+// followed by the messages of the column's other blocks; row group g of the
+// workgroup sums terms [g h, (g + 1) h), h = ceil(terms / 2), in order from
+// +0; the group sums meet in LDS and L = (Q + S0) + S1.  kPart: the partials
+// come from the check pass (A.part); otherwise each is rebuilt from the
+// group's messages, summed in row order from +0, which gives the same bits.
 // Messages of block (r, c) with shift s sit at (j - s) mod Z.
-template <int G, typename Msg, int VPT>
+template <int G, typename Msg, int VPT, bool kPart>
 __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A, int f, int k,
                                               unsigned tile) {
     constexpr int kWavesPerGroup = kBlock / 64 / kVnGroups;
     constexpr int V = kVnLanes * VPT;  // variables per workgroup
+    constexpr int kPB = 4;             // partial loads in flight together
     __shared__ float part[kVnGroups][V];
     const unsigned Z = (unsigned)c.Z;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -888,10 +1049,12 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
     }
     const Msg *msg = reinterpret_cast<const Msg *>(A.msg) + (size_t)f * A.msg_frame;
     const int deg = c.core_deg[k];
-    const int per = (deg + kVnGroups - 1) / kVnGroups;
-    const int b0 = grp * per, b1 = min(deg, b0 + per);
+    const int own = c.core_own[k], ng = c.core_ngrp[k];
+    const int terms = ng + deg - own;
+    const int half = (terms + 1) / 2;
+    const int t0 = grp * half, t1 = min(terms, t0 + half);
     const int32_t *tab = c.core_tab + (size_t)k * c.core_tab_stride;
-    // group 0 also reads Q, issued with its message loads
+    // group 0 also reads Q, issued with its first loads
     const float *llr = A.llr + (size_t)f * c.n + (size_t)c.core_col[k] * Z;
     float q[VPT], p[VPT];
 #pragma unroll
@@ -899,8 +1062,73 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
         q[e] = (grp == 0) ? at(llr, jl[e]) : 0.0f;
         p[e] = 0.0f;
     }
-    for (int b = b0; b < b1; b += G) {
-        float x[VPT][G];
+    // The first batch of message terms (table entries [b0, b1)) is loaded
+    // first, then the partial terms [t0, pe) are loaded and summed, then the
+    // messages are added: the loads of both kinds are in flight together, and
+    // the sum keeps the term order.
+    const int pe = min(t1, ng);
+    const int b0 = own + max(t0, ng) - ng, b1 = own + max(t1, ng) - ng;
+    float x[VPT][G];
+    if (b0 < b1) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int i = min(b0 + u, b1 - 1);
+            const unsigned s = (unsigned)tab[2 * i + 1];
+            const Msg *blk = msg + (unsigned)tab[2 * i];
+#pragma unroll
+            for (int e = 0; e < VPT; ++e) {
+                const unsigned idx = (jl[e] >= s) ? jl[e] - s : jl[e] + Z - s;
+                x[e][u] = msg_load<Msg>(&at(blk, idx));
+            }
+        }
+    }
+    if constexpr (kPart) {
+        const float *pp = A.part + (size_t)f * A.part_frame + (size_t)c.core_grp0[k] * c.Zp;
+        for (int t = t0; t < pe; t += kPB) {
+            float xq[VPT][kPB];
+#pragma unroll
+            for (int u = 0; u < kPB; ++u) {
+                const unsigned row = (unsigned)min(t + u, pe - 1) * (unsigned)c.Zp;
+#pragma unroll
+                for (int e = 0; e < VPT; ++e) xq[e][u] = at(pp, row + jl[e]);
+            }
+#pragma unroll
+            for (int e = 0; e < VPT; ++e)
+#pragma unroll
+                for (int u = 0; u < kPB; ++u) p[e] += (t + u < pe) ? xq[e][u] : 0.0f;
+        }
+    } else {
+        for (int t = t0; t < pe; ++t) {
+            const int c0 = t * kGroupRows, c1 = min(own, c0 + kGroupRows);
+            float xq[VPT][kGroupRows];
+#pragma unroll
+            for (int u = 0; u < kGroupRows; ++u) {
+                const int i = min(c0 + u, c1 - 1);
+                const unsigned s = (unsigned)tab[2 * i + 1];
+                const Msg *blk = msg + (unsigned)tab[2 * i];
+#pragma unroll
+                for (int e = 0; e < VPT; ++e) {
+                    const unsigned idx = (jl[e] >= s) ? jl[e] - s : jl[e] + Z - s;
+                    xq[e][u] = msg_load<Msg>(&at(blk, idx));
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < VPT; ++e) {
+                float sg = 0.0f;
+#pragma unroll
+                for (int u = 0; u < kGroupRows; ++u) sg += (c0 + u < c1) ? xq[e][u] : 0.0f;
+                p[e] += sg;
+            }
+        }
+    }
+    if (b0 < b1) {
+#pragma unroll
+        for (int e = 0; e < VPT; ++e)
+#pragma unroll
+            for (int u = 0; u < G; ++u) p[e] += (b0 + u < b1) ? x[e][u] : 0.0f;
+    }
+    // further batches of message terms
+    for (int b = b0 + G; b < b1; b += G) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int i = min(b + u, b1 - 1);
@@ -935,13 +1163,16 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
     }
 }
 
-// Pack the syndrome bytes into 64-bit words per base row: bit a%64 of word a/64.
+// Pack the syndrome bytes into 64-bit words per base row: bit a%64 of word a/64,
+// for check a of the relabelled row.
 __device__ __forceinline__ void pack_syndrome_work(const CodeDev &c, const uint8_t *syn,
                                                    uint64_t *synbits, size_t syn_frame, int f, int r,
                                                    unsigned tile) {
     const int a = tile * kBlock + threadIdx.x;
     const bool valid = a < c.Z;
-    const int v = valid ? (syn[(size_t)f * c.m + (size_t)r * c.Z + a] & 1) : 0;
+    int j = a - c.row_rot[r];  // the check's index in the code as given
+    j += (j < 0) ? c.Z : 0;
+    const int v = valid ? (syn[(size_t)f * c.m + (size_t)r * c.Z + j] & 1) : 0;
     const unsigned long long bits = wave_ballot(v != 0);
     if ((threadIdx.x & 63) == 0 && valid)
         synbits[(size_t)f * syn_frame + (size_t)r * c.W + (a >> 6)] = bits;

@@ -293,9 +293,11 @@ __device__ __forceinline__ bool res_check_phase(const CodeDev &c, const ResView<
 }
 
 // Variable phase, first half: the row-group sums S0 and S1 of every core
-// variable (the column's first ceil(deg / 2) blocks and the rest, each summed
-// in increasing row order, as in the per-iteration decoder), one wave per
-// (column, 64 variables, group), into part[g].
+// variable, in the column's summation order (the owner-group partials, each
+// rebuilt from its messages in row order from +0, then the other blocks'
+// messages; S0 the first ceil(terms / 2) terms, S1 the rest, each from +0),
+// as in the per-iteration decoder, one wave per (column, 64 variables,
+// group), into part[g].
 template <typename Msg>
 __device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<Msg> &S,
                                                float *const (&part)[kVnGroups]) {
@@ -309,23 +311,39 @@ __device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<M
         const unsigned j = (kc - (unsigned)k * S.W) * 64u + (threadIdx.x & 63u);
         if (j >= Z) continue;
         const int deg = uniform_i32(c.core_deg + k);
-        const int per = (deg + kVnGroups - 1) / kVnGroups;
+        const int own = uniform_i32(c.core_own + k), ng = uniform_i32(c.core_ngrp + k);
+        const int terms = ng + deg - own;
+        const int half = (terms + 1) / 2;
+        const int t0 = g * half, t1 = min(terms, t0 + half);
         const int32_t *tab = c.res_core + (size_t)k * c.res_core_stride;
-        // batches of kResVnBatch blocks: one burst of table loads, then their
-        // LDS loads together.  Entries past the group's end (the next group's,
-        // or zero padding: valid offsets either way) add +0, which leaves a
-        // sum that started at +0 unchanged.
+        auto load = [&](int i) {
+            const unsigned off = (unsigned)uniform_i32(tab + 2 * i);
+            const unsigned s = (unsigned)uniform_i32(tab + 2 * i + 1);
+            const unsigned idx = (j >= s) ? j - s : j + Z - s;
+            return msg_load<Msg>(&S.msg[off + idx]);
+        };
         float p = 0.0f;
-        const int e = min(deg, (g + 1) * per);
-        for (int i0 = g * per; i0 < e; i0 += kResVnBatch) {
+        // partial terms: each group's owned messages, summed from +0
+        for (int t = t0; t < min(t1, ng); ++t) {
+            const int b0 = t * kGroupRows, b1 = min(own, b0 + kGroupRows);
+            float xv[kGroupRows];
+#pragma unroll
+            for (int u2 = 0; u2 < kGroupRows; ++u2) xv[u2] = load(min(b0 + u2, b1 - 1));
+            float sg = 0.0f;
+#pragma unroll
+            for (int u2 = 0; u2 < kGroupRows; ++u2) sg += (b0 + u2 < b1) ? xv[u2] : 0.0f;
+            p += sg;
+        }
+        // message terms: table entries [own + max(t0, ng) - ng, own + max(t1, ng) - ng),
+        // in batches of kResVnBatch blocks: one burst of table loads, then
+        // their LDS loads together.  Entries past the range (valid offsets:
+        // the table is padded) add +0, which leaves a sum that started at +0
+        // unchanged.
+        const int e = own + max(t1, ng) - ng;
+        for (int i0 = own + max(t0, ng) - ng; i0 < e; i0 += kResVnBatch) {
             float xv[kResVnBatch];
 #pragma unroll
-            for (int u2 = 0; u2 < kResVnBatch; ++u2) {
-                const unsigned off = (unsigned)uniform_i32(tab + 2 * (i0 + u2));
-                const unsigned s = (unsigned)uniform_i32(tab + 2 * (i0 + u2) + 1);
-                const unsigned idx = (j >= s) ? j - s : j + Z - s;
-                xv[u2] = msg_load<Msg>(&S.msg[off + idx]);
-            }
+            for (int u2 = 0; u2 < kResVnBatch; ++u2) xv[u2] = load(i0 + u2);
 #pragma unroll
             for (int u2 = 0; u2 < kResVnBatch; ++u2) p += (i0 + u2 < e) ? xv[u2] : 0.0f;
         }
@@ -402,7 +420,10 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     }
     for (unsigned u = wave; u < (unsigned)c.mb * W; u += nw) {
         const unsigned r = u / W, a = (u - r * W) * 64u + lane;
-        const bool v = a < Z && (syn_in[(size_t)r * Z + a] & 1);
+        // check a of the relabelled row is check (a - rot) mod Z as given
+        const unsigned rot = (unsigned)uniform_i32(c.row_rot + r);
+        const unsigned jg = (a >= rot) ? a - rot : a + Z - rot;
+        const bool v = a < Z && (syn_in[(size_t)r * Z + jg] & 1);
         const unsigned long long bits = wave_ballot(v);
         if (lane == 0) syn[u] = bits;
     }

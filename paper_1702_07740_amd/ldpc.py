@@ -49,6 +49,7 @@ class CodeInfo(ctypes.Structure):
         ("edges", ctypes.c_int64), ("state_edges", ctypes.c_int64),
         ("core_cols", ctypes.c_int32), ("deg1_cols", ctypes.c_int32),
         ("deg0_cols", ctypes.c_int32), ("max_row_degree", ctypes.c_int32),
+        ("owned_edges", ctypes.c_int64), ("owner_groups", ctypes.c_int32),
     ]
 
 
