@@ -533,12 +533,20 @@ def workload_serving(torch, ldpc, args):
     trace = serve.poisson_trace(len(pools), lam, args.duration, seed=11)
     print(f"[bench] serving: capacity {cap:.1f} req/s, {len(trace)} requests", file=sys.stderr,
           flush=True)
-    eng, _ = serve.run_engine(ldpc, torch, pools, copy.deepcopy(trace), 200 << 30)
-    print(f"[bench] serving: engine {eng}", file=sys.stderr, flush=True)
+    caps = {}
+    for c in [int(float(x)) for x in args.serve_caps.split(",")]:
+        st_c, _ = serve.run_engine(ldpc, torch, pools, copy.deepcopy(trace), 200 << 30,
+                                   max_step_edges=c)
+        caps[str(c)] = st_c
+        print(f"[bench] serving: engine, 200 GB budget, step cap {c} edges: {st_c}",
+              file=sys.stderr, flush=True)
+    eng = caps[str(int(float(args.serve_caps.split(",")[0])))]
     small, _ = serve.run_engine(ldpc, torch, pools, copy.deepcopy(trace), 256 << 20)
     print(f"[bench] serving: engine, 256 MB budget {small}", file=sys.stderr, flush=True)
-    one, _ = serve.run_one_at_a_time(ldpc, torch, pools, copy.deepcopy(trace))
-    print(f"[bench] serving: one at a time {one}", file=sys.stderr, flush=True)
+    one = None
+    if not args.no_one_at_a_time:
+        one, _ = serve.run_one_at_a_time(ldpc, torch, pools, copy.deepcopy(trace))
+        print(f"[bench] serving: one at a time {one}", file=sys.stderr, flush=True)
     return {
         "metric": "serving: raw decoded Mbit/s and p50/p99 latency, Poisson mixed-code requests",
         "value": round(eng["mbit_s"], 3), "unit": "Mbit/s", "n_gpus": 1, "steps": len(trace),
@@ -548,9 +556,11 @@ def workload_serving(torch, ldpc, args):
                                f"measured capacity {cap:.1f} req/s) for {args.duration} s; R in "
                                "{0.02,0.05,0.1}, Z in {1024,2048,4096,6667}, 1-4 frames, "
                                "threshold + 0.3 dB, max 100 iterations",
-                   "budget_bytes": 200 << 30},
+                   "budget_bytes": 200 << 30,
+                   "max_step_edges": int(float(args.serve_caps.split(",")[0]))},
         "latency_ms": {"p50": eng["p50_ms"], "p99": eng["p99_ms"]},
-        "engine": eng, "engine_256MB_budget": small, "one_at_a_time_fp32": one,
+        "engine": eng, "engine_by_step_cap": caps, "engine_256MB_budget": small,
+        "one_at_a_time_fp32": one,
     }
 
 
@@ -573,6 +583,10 @@ def main():
                          "engine batch; frontend: 8-D reconciliation + FP16 decode; serving: "
                          "Poisson requests through the engine")
     ap.add_argument("--duration", type=float, default=60.0, help="serving run length (s)")
+    ap.add_argument("--serve-caps", default="16e6,0",
+                    help="serving: engine step caps in edge visits (first = reported; 0 = none)")
+    ap.add_argument("--no-one-at-a-time", action="store_true",
+                    help="serving: skip the one-request-at-a-time baseline")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="serving arrival rate as a fraction of measured capacity")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -286,6 +286,12 @@ typedef struct {
     int32_t early_stop;      /* as ldpc_decode_opts.early_stop                         */
     int32_t checks_per_thread; /* check-kernel schedule as in ldpc_decode_opts      */
     void *stream;            /* hipStream_t for all engine work; NULL = null stream    */
+    int64_t max_step_edges;  /* latency cap: most edge visits per engine step, the sum
+                                over admitted requests of frames x Tanner-graph edges
+                                (blocks * Z); a step's time grows with it, and so does
+                                every admitted request's latency (iterations x step
+                                time).  0 = no cap.  A request above the cap is still
+                                admitted when nothing else is in flight.           */
 } ldpc_engine_config;
 
 /* Create an engine on the current device.  Errors: LDPC_EINVAL (null, budget 0,

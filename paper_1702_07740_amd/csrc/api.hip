@@ -782,8 +782,12 @@ int ldpc_engine_create(const ldpc_engine_config *cfg, ldpc_engine **out) {
     if (cpt != 1 && cpt != 2 && cpt != 4)
         return fail_with(LDPC_EINVAL, "checks_per_thread = %d is not 0, 1, 2 or 4",
                          cfg->checks_per_thread);
+    if (cfg->max_step_edges < 0)
+        return fail_with(LDPC_EINVAL, "max_step_edges = %lld is negative",
+                         (long long)cfg->max_step_edges);
     ldpc_engine *en = new (std::nothrow) ldpc_engine();
     if (!en) return fail_with(LDPC_ENOMEM, "host allocation failed");
+    en->e.max_step_edges = cfg->max_step_edges;
     hipError_t e = hipGetDevice(&en->e.device);
     if (e == hipSuccess)
         e = en->e.init(cfg->hbm_budget_bytes, cfg->max_slots, cfg->msg_fp16 != 0,

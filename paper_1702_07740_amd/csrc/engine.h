@@ -79,6 +79,7 @@ struct Engine {
     };
 
     size_t budget_bytes = 0, in_use = 0;
+    int64_t max_step_edges = 0, active_edges = 0;  // latency cap on the work of one step
     int max_slots = 0;
     bool fp16 = false, early_stop = true;
     int cpt = 4;  // checks per thread of the check kernel (1, 2, 4)

@@ -357,9 +357,18 @@ int64_t Engine::submit(const Request &rq) {
     return r.ticket;
 }
 
+// Edge visits of one iteration of a request: frames x (stored + degree-1
+// blocks) x Z.
+static int64_t request_edges(const Request &rq) {
+    return (int64_t)rq.F * (int64_t)(rq.c.NS + rq.c.ND1) * rq.c.Z;
+}
+
 bool Engine::admit_one(const Request &rq, int s) {
     const size_t need = request_bytes(rq.c, rq.F, rq.T, fp16);
     if (in_use + need > budget_bytes) return false;
+    const int64_t work = request_edges(rq);
+    if (max_step_edges > 0 && active_edges > 0 && active_edges + work > max_step_edges)
+        return false;
     void *p = arena.alloc(need);
     if (!p) {
         // the chunks may not outgrow the budget: first return idle chunks
@@ -373,6 +382,7 @@ bool Engine::admit_one(const Request &rq, int s) {
         if (!p) return false;
     }
     in_use += need;
+    active_edges += work;
     Slot &sl = slot[s];
     sl.active = true;
     sl.all_done = false;
@@ -454,6 +464,7 @@ void Engine::retire(int s) {
     // later kernels on this stream run after the read-out, so the space can be reused now
     arena.release(sl.mem, sl.mem_bytes);
     in_use -= sl.mem_bytes;
+    active_edges -= request_edges(sl.req);
     sl.active = false;
     table_dirty = true;
 }

@@ -68,6 +68,7 @@ class EngineConfig(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
         ("msg_fp16", ctypes.c_int32), ("early_stop", ctypes.c_int32),
         ("checks_per_thread", ctypes.c_int32), ("stream", ctypes.c_void_p),
+        ("max_step_edges", ctypes.c_int64),
     ]
 
 
@@ -348,12 +349,13 @@ class Engine:
     """
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, msg_fp16=False,
-                 early_stop=True, stream=None, checks_per_thread=0):
+                 early_stop=True, stream=None, checks_per_thread=0, max_step_edges=0):
         import torch
         lib = load()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cfg = EngineConfig(int(hbm_budget_bytes), int(max_slots), int(bool(msg_fp16)),
-                           int(bool(early_stop)), int(checks_per_thread), self.stream.cuda_stream)
+                           int(bool(early_stop)), int(checks_per_thread), self.stream.cuda_stream,
+                           int(max_step_edges))
         h = ctypes.c_void_p()
         _check(lib.ldpc_engine_create(ctypes.byref(cfg), ctypes.byref(h)), "ldpc_engine_create")
         self._h = h

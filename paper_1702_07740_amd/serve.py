@@ -98,9 +98,14 @@ def _inputs(pools, r):
 
 
 def run_engine(ldpc, torch, pools, trace, budget_bytes, max_slots=64, msg_fp16=False,
-               keep_outputs=False):
-    """Serve `trace` in real time through the engine.  Returns stats (and outputs)."""
-    eng = ldpc.Engine(budget_bytes, max_slots=max_slots, msg_fp16=msg_fp16)
+               keep_outputs=False, max_step_edges=0):
+    """Serve `trace` in real time through the engine.  Returns stats (and outputs).
+
+    max_step_edges caps the work of one engine step (frames x edges of the
+    admitted requests), which bounds the step time and so the latency of every
+    admitted request; requests beyond it wait in the queue."""
+    eng = ldpc.Engine(budget_bytes, max_slots=max_slots, msg_fp16=msg_fp16,
+                      max_step_edges=max_step_edges)
     by_ticket, outputs = {}, {}
     pending = list(trace)
     pending.reverse()

@@ -576,3 +576,26 @@ def test_schedule_does_not_change_results(ldpc, oracle_mod, Z):
         assert np.array_equal(u, v)
     with pytest.raises(ldpc.LdpcError):
         g.decode(_dev(Q), _dev(s), 5, checks_per_thread=3)
+
+
+@pytest.mark.parametrize("rate,Z", [(0.02, 64), (0.05, 100), (0.1, 7)])
+def test_owner_groups_of_the_templates(ldpc, oracle_mod, rate, Z):
+    """Every type-2 row (two core blocks, one degree-1 block) owns one core
+    block, the 6 core columns own equally many rows, and each column's owned
+    rows form groups of at most 24; codes without such rows have none.  The
+    relabelling these groups rest on leaves the syndrome of a word unchanged:
+    the library's H x equals the oracle's for random words."""
+    base = synth.template_for_rate(rate, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    n_type2 = synth.N_DEG1_FOR_RATE[rate]
+    per_col = n_type2 // synth.N_CORE
+    assert g.info["owned_edges"] == n_type2 * Z
+    assert g.info["owner_groups"] == synth.N_CORE * -(-per_col // 24)
+    o = oracle_mod.OracleCode(base, Z)
+    x = np.random.default_rng(7).integers(0, 2, size=(3, g.n), dtype=np.uint8)
+    s = g.syndrome(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.array_equal(s, o.syndrome(x))
+    # a code with no type-2 rows: every block non-zero, every column of degree 3
+    dense = np.random.default_rng(3).integers(0, Z, size=(3, 6)).astype(np.int32)
+    info = ldpc.Code(dense, Z).info
+    assert info["owner_groups"] == 0 and info["owned_edges"] == 0

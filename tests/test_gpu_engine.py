@@ -125,6 +125,43 @@ def test_engine_budget_bounds_admission(ldpc, oracle_mod):
     eng.close()
 
 
+def test_engine_step_cap_bounds_admission(ldpc, oracle_mod):
+    """A step cap of 2.5 requests' edge visits: never more than 2 in flight,
+    results unchanged; a request above the cap still runs when alone."""
+    Z, F, T = 128, 2, 50
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    reqs = []
+    for i in range(5):
+        x, Q = synth.biawgn_frames(o.n, F, -13.8, seed=720 + i)
+        reqs.append((_dev(Q), _dev(o.syndrome(x))))
+    work = F * g.info["edges"]
+    for cap, limit in ((2 * work + work // 2, 2), (work // 3, 1)):
+        eng = ldpc.Engine(1 << 30, max_slots=8, max_step_edges=cap)
+        _say("engine step cap", cap)
+        tickets = [eng.submit(g, Q, s, T) for Q, s in reqs]
+        most, done = 0, {}
+        for _ in range(100000):
+            for t in eng.poll():
+                done[t] = eng.result(t)
+            if len(done) == len(tickets):
+                break
+            active, queued = eng.step()
+            most = max(most, active)
+            if active == 0 and queued == 0:
+                torch.cuda.synchronize()
+        assert len(done) == len(tickets)
+        assert most == limit
+        for (Q, s), t in zip(reqs, tickets):
+            b0, i0, c0 = _alone(g, Q, s, T, False)
+            assert np.array_equal(done[t][0].cpu().numpy(), b0)
+            assert np.array_equal(done[t][1].cpu().numpy(), i0)
+        eng.close()
+    with pytest.raises(ldpc.LdpcError):
+        ldpc.Engine(1 << 20, max_slots=2, max_step_edges=-1)
+
+
 def test_engine_edge_cases(ldpc, oracle_mod):
     Z = 64
     base = synth.template_base(144, Z, seed=1)
