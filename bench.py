@@ -435,6 +435,10 @@ def workload_small(torch, ldpc, args):
     ws16 = code.alloc_workspace(F, T, msg_fp16=True)
     res16_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws16, out=out, msg_fp16=True,
                                          schedule="resident"), args.steps)
+    split_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws, out=out, schedule="split"),
+                     args.steps)
+    split16_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws16, out=out, msg_fp16=True,
+                                           schedule="split"), args.steps)
     eager_ms = timed(lambda: code.decode(dQ, ds, T, workspace=ws, out=out, schedule="launches"),
                      args.steps)
     side = torch.cuda.Stream()
@@ -453,7 +457,9 @@ def workload_small(torch, ldpc, args):
         dQs = torch.from_numpy(Qs).cuda()
         dss = code.syndrome(torch.from_numpy(xs).cuda())
         wss = code.alloc_workspace(Fs, T)
-        for sch in ("resident", "launches"):
+        for sch in ("resident", "launches", "split"):
+            if sch == "split" and Fs > 256:
+                continue
             ms = timed(lambda: code.decode(dQs, dss, T, workspace=wss, schedule=sch),
                        max(3, args.steps // 4))
             sweep.setdefault(str(Fs), {})[sch] = {"ms": ms, "mbit_s": round(Fs * code.n / ms / 1e3, 3)}
@@ -468,6 +474,8 @@ def workload_small(torch, ldpc, args):
                                f"max {T} iterations, early stop; automatic schedule ({auto})"},
         "resident": {"ms_per_step": res_ms, "mbit_s": round(bits / res_ms / 1e3, 3)},
         "resident_fp16": {"ms_per_step": res16_ms, "mbit_s": round(bits / res16_ms / 1e3, 3)},
+        "split": {"ms_per_step": split_ms, "mbit_s": round(bits / split_ms / 1e3, 3)},
+        "split_fp16": {"ms_per_step": split16_ms, "mbit_s": round(bits / split16_ms / 1e3, 3)},
         "launches_eager": {"ms_per_step": eager_ms, "mbit_s": round(bits / eager_ms / 1e3, 3)},
         "launches_graph": {"ms_per_step": graph_ms, "mbit_s": round(bits / graph_ms / 1e3, 3)},
         "resident_frames": sweep,

@@ -133,18 +133,31 @@ typedef struct {
  *            latency-bound.  Needs llr_out and timing_events unset and the
  *            frame's state within one workgroup's LDS (160 KB on MI355X:
  *            state edges * (4 or 2 bytes) + core variables * 16 + bit arrays).
+ *  SPLIT     one cooperative launch for the whole decode with up to 4
+ *            co-resident workgroups per frame: the frame's messages in device
+ *            memory (two buffers, by iteration parity), every workgroup holding
+ *            the frame's core totals in LDS, one barrier across a frame's
+ *            workgroups per iteration: for a few frames of a small code, where
+ *            one workgroup per frame leaves most of the chip idle.  Needs
+ *            llr_out and timing_events unset, at most 256 frames, and a frame
+ *            state of at most 160 KB (as RESIDENT).
  *  AUTO      RESIDENT when it is possible and a cost model of both, fitted
  *            to measurements, favours it (many frames of a small code), else
  *            LAUNCHES.
  */
-enum { LDPC_SCHEDULE_AUTO = 0, LDPC_SCHEDULE_LAUNCHES = 1, LDPC_SCHEDULE_RESIDENT = 2 };
+enum {
+    LDPC_SCHEDULE_AUTO = 0,
+    LDPC_SCHEDULE_LAUNCHES = 1,
+    LDPC_SCHEDULE_RESIDENT = 2,
+    LDPC_SCHEDULE_SPLIT = 3
+};
 
 /* Fill opts with the defaults {early_stop=1, check_from_iter=0, msg_fp16=0,
  * checks_per_thread=0, llr_out=NULL, timing_events=NULL, n_timing_events=0,
  * schedule=LDPC_SCHEDULE_AUTO}. */
 void ldpc_decode_opts_init(ldpc_decode_opts *opts);
 
-/* The schedule (LDPC_SCHEDULE_LAUNCHES or LDPC_SCHEDULE_RESIDENT) that
+/* The schedule (LDPC_SCHEDULE_LAUNCHES, _RESIDENT or _SPLIT) that
  * ldpc_decode_batch runs for F frames with these options (NULL = defaults).
  *   schedule_out  host
  * Errors: LDPC_EINVAL (null, F outside [1, 65535], schedule out of range),

@@ -584,8 +584,15 @@ int resolve_schedule(const ldpc_code *code, int F, const ldpc_decode_opts &o, in
         o.checks_per_thread != 4)
         return fail_with(LDPC_EINVAL, "checks_per_thread = %d is not 0, 1, 2 or 4",
                          o.checks_per_thread);
-    if (o.schedule < LDPC_SCHEDULE_AUTO || o.schedule > LDPC_SCHEDULE_RESIDENT)
-        return fail_with(LDPC_EINVAL, "schedule = %d is not 0, 1 or 2", o.schedule);
+    if (o.schedule < LDPC_SCHEDULE_AUTO || o.schedule > LDPC_SCHEDULE_SPLIT)
+        return fail_with(LDPC_EINVAL, "schedule = %d is not 0, 1, 2 or 3", o.schedule);
+    if (o.schedule == LDPC_SCHEDULE_SPLIT &&
+        (o.llr_out || o.timing_events || F > ldpc::kSplitMaxFrames ||
+         !ldpc::split_offered(code->dev, o.msg_fp16 != 0)))
+        return fail_with(LDPC_EUNSUPPORTED,
+                         "split schedule: needs llr_out and timing_events unset, at most %d "
+                         "frames and a frame state of at most %zu bytes",
+                         ldpc::kSplitMaxFrames, ldpc::kSplitMaxStateBytes);
     const bool possible = !o.llr_out && !o.timing_events && code->dev.res_units > 0 &&
                           ldpc::resident_layout(code->dev, o.msg_fp16 != 0).total <= code->lds_limit;
     if (o.schedule == LDPC_SCHEDULE_RESIDENT && !possible)
@@ -697,11 +704,10 @@ int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const 
     l.ws = static_cast<char *>(workspace);
     l.events = reinterpret_cast<hipEvent_t *>(o.timing_events);
     l.stream = static_cast<hipStream_t>(stream);
-    hipError_t e = sched == LDPC_SCHEDULE_RESIDENT
-                       ? ldpc::enqueue_resident(l, ldpc::work_layout(l.c, F, max_iters, l.fp16 != 0,
-                                                                     false),
-                                                code->lds_limit)
-                       : ldpc::enqueue_decode(l);
+    const ldpc::WorkLayout WL = ldpc::work_layout(l.c, F, max_iters, l.fp16 != 0, false);
+    hipError_t e = sched == LDPC_SCHEDULE_RESIDENT ? ldpc::enqueue_resident(l, WL, code->lds_limit)
+                   : sched == LDPC_SCHEDULE_SPLIT  ? ldpc::enqueue_split(l, WL)
+                                                   : ldpc::enqueue_decode(l);
     if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
     return LDPC_OK;
 }

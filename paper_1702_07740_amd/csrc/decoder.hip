@@ -400,6 +400,12 @@ WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr)
     L.part_frame = (size_t)c.n_groups * c.Zp;
     L.part = off;
     off = align256(off + (size_t)F * L.part_frame * 4);
+    L.split_frame = split_offered(c, fp16) ? (size_t)c.NS * c.Z : 0;
+    L.split_msg = off;
+    off = align256(off + (size_t)F * L.split_frame * (fp16 ? 2 : 4));
+    // frame-split schedule: F arrival counters, then (T + 2) * F vote flags
+    L.team = off;
+    off = align256(off + (size_t)F * (T + 3) * 4);
     L.total = off;
     return L;
 }

@@ -169,8 +169,10 @@ struct CodeDev {
 
 // Byte offsets of the decode workspace for F frames and T iterations.
 struct WorkLayout {
-    size_t msg, tot, psi, d1bits, synbits, fail, d1post, part, total;
+    size_t msg, tot, psi, d1bits, synbits, fail, d1post, part, split_msg, team, total;
     size_t part_frame;     // floats per frame (group partials, n_groups * Zp)
+    size_t split_frame;    // messages per frame of the frame-split schedule's second
+                           // buffer (NS * Z, or 0 where that schedule is not offered)
     size_t msg_frame;      // elements per frame
     size_t tot_frame;      // floats per frame
     size_t psi_frame;      // floats per frame (degree-1 inputs; also posteriors)
@@ -222,6 +224,18 @@ struct ResidentArgs {
 // Enqueue a whole decode as one resident launch (no posteriors, no per-pass
 // events).  hipErrorInvalidValue if the state exceeds lds_limit bytes.
 hipError_t enqueue_resident(const DecodeLaunch &l, const WorkLayout &W, size_t lds_limit);
+
+// Frame-split schedule (resident.hip): K co-resident workgroups per frame run
+// every iteration in one cooperative launch, the frame's messages in global
+// memory (two buffers, by iteration parity), the core totals in every
+// workgroup's LDS, one barrier across the frame's workgroups per iteration.
+// Offered where the frame's state is at most kSplitMaxStateBytes.
+constexpr size_t kSplitMaxStateBytes = 160 * 1024;
+constexpr int kSplitMaxTeam = 4;
+constexpr int kSplitMaxFrames = 256;  // one 1024-thread workgroup per CU at most
+bool split_offered(const CodeDev &c, bool fp16);
+int split_team(int F);  // workgroups per frame for F frames
+hipError_t enqueue_split(const DecodeLaunch &l, const WorkLayout &W);
 hipError_t enqueue_syndrome(const CodeDev &c, int F, const uint8_t *bits, uint8_t *syn,
                             hipStream_t stream);
 hipError_t enqueue_reconciliation_llr(int d, int F, int n, const float *x, const float *m,

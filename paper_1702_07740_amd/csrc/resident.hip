@@ -39,7 +39,9 @@ constexpr int kResThreads = 1024;  // 16 wave64s: four per SIMD of the one CU
 
 template <typename Msg>
 struct ResView {
-    Msg *msg;            // [NS][Z] messages, check order (LDS)
+    Msg *msg;            // [NS][Z] messages, check order (LDS), written by the check phase
+    const Msg *msg_in;   // where the check phase reads the previous messages (= msg here;
+                         // the other buffer of a pair in the frame-split schedule)
     float *tot;          // [NC][Z] core totals, base 2 (LDS)
     const float *q;      // [NC][Z] channel LLRs of the core variables (LDS)
     const uint64_t *syn; // [mb][W] packed syndrome bits (LDS)
@@ -79,7 +81,7 @@ __device__ __forceinline__ bool res_fixed(const ResView<Msg> &S, const int32_t *
                 j -= (j >= Z) ? Z : 0u;
                 const float lt = S.tot[o0 + j];
                 idx[q][k] = o1 + a;
-                const float mo = UPDATE ? msg_load<Msg>(&S.msg[o1 + al]) : 0.0f;
+                const float mo = UPDATE ? msg_load<Msg>(&S.msg_in[o1 + al]) : 0.0f;
                 x[q][k] = lt - mo;
                 dec[q][k] = lt < 0.0f;
             } else {
@@ -172,7 +174,7 @@ __device__ __forceinline__ bool res_generic(const CodeDev &c, const ResView<Msg>
             j -= (j >= Z) ? Z : 0u;
             const float lt = S.tot[(unsigned)uniform_i32(c.blk_core + b) * Z + j];
             idx[k] = ref * Z + a;
-            const float mo = UPDATE ? msg_load<Msg>(&S.msg[ref * Z + al]) : 0.0f;
+            const float mo = UPDATE ? msg_load<Msg>(&S.msg_in[ref * Z + al]) : 0.0f;
             x[k] = lt - mo;
             dec[k] = lt < 0.0f;
         } else {
@@ -255,14 +257,14 @@ __device__ __forceinline__ bool res_unit(const CodeDev &c, const ResView<Msg> &S
 }
 
 // Check phase of one frame.  The units (row, chunk of 64 checks) are listed
-// with the rows in class order; the waves take pairs of consecutive units in
-// turn, and a pair of one common class runs as one two-unit chain.
+// with the rows in class order; the frame's waves (wave index `wave` of `nw`,
+// across all of the frame's workgroups) take pairs of consecutive units in
+// turn, and a pair of one common class runs as one two-unit chain.  A unit's
+// messages and decision word belong to one wave for the whole decode.
 template <bool UPDATE, typename Msg, bool GENERIC>
 __device__ __forceinline__ bool res_check_phase(const CodeDev &c, const ResView<Msg> &S,
                                                 const uint64_t *dprev, uint64_t *dcur,
-                                                const PhiConsts &PK) {
-    const int nw = (int)(blockDim.x >> 6);
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+                                                const PhiConsts &PK, int wave, int nw) {
     const int units = c.res_units;
     bool bad = false;
     for (int u = 2 * wave; u < units; u += 2 * nw) {
@@ -308,17 +310,32 @@ __device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<M
         const int g = (int)(u % kVnGroups);
         const unsigned kc = u / kVnGroups;
         const int k = (int)(kc / S.W);
-        const unsigned j = (kc - (unsigned)k * S.W) * 64u + (threadIdx.x & 63u);
-        if (j >= Z) continue;
+        const unsigned jv = (kc - (unsigned)k * S.W) * 64u + (threadIdx.x & 63u);
+        // every lane stays active through the loads (the table window is one
+        // pair per lane); lanes past Z read variable Z - 1 and store nothing
+        const bool valid = jv < Z;
+        const unsigned j = valid ? jv : Z - 1;
         const int deg = uniform_i32(c.core_deg + k);
         const int own = uniform_i32(c.core_own + k), ng = uniform_i32(c.core_ngrp + k);
         const int terms = ng + deg - own;
         const int half = (terms + 1) / 2;
         const int t0 = g * half, t1 = min(terms, t0 + half);
         const int32_t *tab = c.res_core + (size_t)k * c.res_core_stride;
+        // The column's (offset, shift) pairs, 64 at a time, one per lane
+        // (one vector load instead of a chain of scalar loads); a block's
+        // pair is then read from its lane.
+        int w0 = -(1 << 30), voff = 0, vsh = 0;
+        auto window = [&](int lo, int hi) {  // make pairs [lo, hi) readable, hi - lo <= 64
+            if (lo < w0 || hi > w0 + 64) {
+                w0 = lo;
+                const int e = w0 + (int)(threadIdx.x & 63u);
+                voff = e < deg ? tab[2 * e] : 0;
+                vsh = e < deg ? tab[2 * e + 1] : 0;
+            }
+        };
         auto load = [&](int i) {
-            const unsigned off = (unsigned)uniform_i32(tab + 2 * i);
-            const unsigned s = (unsigned)uniform_i32(tab + 2 * i + 1);
+            const unsigned off = (unsigned)__builtin_amdgcn_readlane(voff, i - w0);
+            const unsigned s = (unsigned)__builtin_amdgcn_readlane(vsh, i - w0);
             const unsigned idx = (j >= s) ? j - s : j + Z - s;
             return msg_load<Msg>(&S.msg[off + idx]);
         };
@@ -326,6 +343,7 @@ __device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<M
         // partial terms: each group's owned messages, summed from +0
         for (int t = t0; t < min(t1, ng); ++t) {
             const int b0 = t * kGroupRows, b1 = min(own, b0 + kGroupRows);
+            window(b0, b0 + kGroupRows);
             float xv[kGroupRows];
 #pragma unroll
             for (int u2 = 0; u2 < kGroupRows; ++u2) xv[u2] = load(min(b0 + u2, b1 - 1));
@@ -341,13 +359,14 @@ __device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<M
         // unchanged.
         const int e = own + max(t1, ng) - ng;
         for (int i0 = own + max(t0, ng) - ng; i0 < e; i0 += kResVnBatch) {
+            window(i0, i0 + kResVnBatch);
             float xv[kResVnBatch];
 #pragma unroll
             for (int u2 = 0; u2 < kResVnBatch; ++u2) xv[u2] = load(i0 + u2);
 #pragma unroll
             for (int u2 = 0; u2 < kResVnBatch; ++u2) p += (i0 + u2 < e) ? xv[u2] : 0.0f;
         }
-        part[g][(unsigned)k * Z + j] = p;
+        if (valid) part[g][(unsigned)k * Z + j] = p;
     }
 }
 
@@ -374,6 +393,7 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     const unsigned Z = (unsigned)c.Z, W = (unsigned)c.W, Zp = (unsigned)c.Zp;
     ResView<Msg> S;
     S.msg = reinterpret_cast<Msg *>(lds);
+    S.msg_in = S.msg;
     S.tot = reinterpret_cast<float *>(lds + A.lds_tot);
     float *qc = reinterpret_cast<float *>(lds + A.lds_q);
     S.q = qc;
@@ -437,7 +457,8 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     for (int t = 1; t <= T; ++t) {
         const bool vote = checked(t - 1);
         const bool bad = res_check_phase<true, Msg, kGeneric>(c, S, d1 + ((t - 1) & 1) * d1n,
-                                                    d1 + (t & 1) * d1n, PK);
+                                                              d1 + (t & 1) * d1n, PK, (int)wave,
+                                                              (int)nw);
         if (vote && wave_ballot(bad) != 0ull && lane == 0) flag[t & 1] = 1;
         __syncthreads();
         if (vote && flag[t & 1] == 0) {
@@ -456,8 +477,8 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     }
     if (!stopped) {
         // the check of the last iteration (the channel decisions when T = 0)
-        const bool bad =
-            res_check_phase<false, Msg, kGeneric>(c, S, d1 + (T & 1) * d1n, nullptr, PK);
+        const bool bad = res_check_phase<false, Msg, kGeneric>(c, S, d1 + (T & 1) * d1n, nullptr,
+                                                               PK, (int)wave, (int)nw);
         if (wave_ballot(bad) != 0ull && lane == 0) flag[(T + 1) & 1] = 1;
         __syncthreads();
         conv = flag[(T + 1) & 1] == 0;
@@ -486,7 +507,266 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     }
 }
 
+// ---------------------------------------------------------------------------
+// Frame-split schedule.  K workgroups share a frame: the check phase's units
+// are dealt over all of the frame's waves, and every workgroup recomputes the
+// frame's core totals into its own LDS from the messages in global memory
+// (the same row-group sums and totals as above, so the same bits).  One
+// barrier across the frame's workgroups per iteration separates the check
+// phase from the totals.  Messages alternate between two buffers by iteration
+// parity: the check phase of iteration t reads the messages of t - 1 from one
+// and writes those of t to the other, so a workgroup that starts iteration
+// t + 1 while another still sums the messages of t writes only the buffer
+// nobody reads.  Everything else the check phase touches (a unit's messages,
+// its decision word) belongs to one wave for the whole decode.
+
+constexpr int kSplitThreads = 1024;
+constexpr unsigned kSplitSpinLimit = 1u << 22;  // polls of about 60 ns: a quarter second
+
+struct SplitArgs {
+    const float *llr;          // [F][n]
+    const uint8_t *syndrome;   // [F][m]
+    float *psi;                // [F][ND1][Zp]
+    void *msg[2];              // two message buffers, [F][NS][Z] each
+    uint64_t *synbits;         // [F][mb][W]
+    uint64_t *d1[2];           // [F][ND1][W] each, by iteration parity
+    int32_t *team;             // [F] arrival counters, then [T + 2][F] vote flags; zero at launch
+    uint8_t *bits_out;
+    int32_t *iters_out;
+    uint8_t *conv_out;
+    size_t msg_frame, psi_frame, d1_frame, syn_frame;
+    int T, early_stop, check_from, K, F;
+    unsigned lds_q, lds_part;  // LDS: totals at 0, core LLRs, row-group sums
+};
+
+// Barrier across the workgroups of one frame: every wave's stores leave
+// first; one thread publishes them to the device (agent-scope release),
+// arrives, waits for all K arrivals of this round (a bounded wait), and makes
+// the others' stores visible to the workgroup (agent-scope acquire).  Returns
+// false if the wait ran out, which the caller reports as a failed decode.
+__device__ __forceinline__ bool team_barrier(int32_t *ctr, int target) {
+    __shared__ int ok_s;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        unsigned n = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++n > kSplitSpinLimit) {
+                ok = 0;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+}
+
+__device__ __forceinline__ int32_t agent_load(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename Msg, bool kGeneric>
+__global__ __launch_bounds__(kSplitThreads) void split_decode(CodeDev c, SplitArgs A) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    // workgroup g: XCD g mod 8 (the hardware's dealing order); the K members
+    // of a frame sit on one XCD
+    const unsigned g = blockIdx.x, x = g % 8u, j = g / 8u, K = (unsigned)A.K;
+    const unsigned k = j % K;
+    const int f = (int)(x + 8u * (j / K));
+    if (f >= A.F) return;  // padding workgroups of a frame that does not exist
+    const unsigned Z = (unsigned)c.Z, W = (unsigned)c.W, Zp = (unsigned)c.Zp;
+    const unsigned nt = blockDim.x, nw = nt >> 6, lane = threadIdx.x & 63u;
+    const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gw = (int)(k * nw + wave), NW = (int)(K * nw);
+    const unsigned gt = k * nt + threadIdx.x, NT = K * nt;
+    const PhiConsts PK = phi_consts();
+    float *tot = reinterpret_cast<float *>(lds);
+    float *qc = reinterpret_cast<float *>(lds + A.lds_q);
+    float *const part[kVnGroups] = {reinterpret_cast<float *>(lds + A.lds_part),
+                                    reinterpret_cast<float *>(lds + A.lds_part) + c.NC * c.Z};
+    Msg *mb[2] = {reinterpret_cast<Msg *>(A.msg[0]) + (size_t)f * A.msg_frame,
+                  reinterpret_cast<Msg *>(A.msg[1]) + (size_t)f * A.msg_frame};
+    uint64_t *d1[2] = {A.d1[0] + (size_t)f * A.d1_frame, A.d1[1] + (size_t)f * A.d1_frame};
+    uint64_t *syn = A.synbits + (size_t)f * A.syn_frame;
+    float *psi = A.psi + (size_t)f * A.psi_frame;
+    ResView<Msg> S;
+    S.msg = mb[1];
+    S.msg_in = mb[0];
+    S.tot = tot;
+    S.q = qc;
+    S.syn = syn;
+    S.psi = psi;
+    S.Z = Z;
+    S.W = W;
+    S.Zp = Zp;
+    int32_t *ctr = A.team + f;
+    int32_t *flags = A.team + A.F;  // [T + 2][F]
+    const float *llr = A.llr + (size_t)f * c.n;
+    const uint8_t *syn_in = A.syndrome + (size_t)f * c.m;
+    int epoch = 0;
+    bool ok = true;
+
+    // Set-up over the frame's workgroups: messages of iteration 0 (zero), Psi
+    // and the channel-sign decision bits of the degree-1 variables, packed
+    // syndrome; per workgroup: core LLRs and the totals of iteration 0.
+    for (unsigned i = gt; i < (unsigned)c.NS * Z; i += NT) msg_store<Msg>(&mb[0][i], 0.0f);
+    for (unsigned u = (unsigned)gw; u < (unsigned)c.ND1 * W; u += (unsigned)NW) {
+        const unsigned kk = u / W, a = (u - kk * W) * 64u + lane;
+        bool neg = false;
+        if (a < Z) {
+            unsigned jj = a + (unsigned)uniform_i32(c.d1_shift + kk);
+            jj -= (jj >= Z) ? Z : 0u;
+            const float q = llr[(size_t)uniform_i32(c.d1_col + kk) * Z + jj];
+            psi[kk * Zp + a] = d1_input(q, uniform_i32(c.d1_tdom + kk) != 0, PK);
+            neg = q < 0.0f;
+        }
+        const unsigned long long bits = wave_ballot(neg);
+        if (lane == 0) d1[0][u] = bits;
+    }
+    for (unsigned u = (unsigned)gw; u < (unsigned)c.mb * W; u += (unsigned)NW) {
+        const unsigned r = u / W, a = (u - r * W) * 64u + lane;
+        const unsigned rot = (unsigned)uniform_i32(c.row_rot + r);
+        const unsigned jg = (a >= rot) ? a - rot : a + Z - rot;
+        const bool v = a < Z && (syn_in[(size_t)r * Z + jg] & 1);
+        const unsigned long long bits = wave_ballot(v);
+        if (lane == 0) syn[u] = bits;
+    }
+    for (unsigned i = threadIdx.x; i < (unsigned)c.NC * Z; i += nt) {
+        const unsigned kk = i / Z, jj = i - kk * Z;
+        const float q = llr[(size_t)c.core_col[kk] * Z + jj];
+        qc[i] = q;
+        tot[i] = q * kLog2e;
+    }
+    ok &= team_barrier(ctr, (int)K * ++epoch);
+
+    const int T = A.T;
+    auto checked = [&](int t) { return t == T || (A.early_stop && t >= A.check_from); };
+    int it = T, conv = 0;
+    bool stopped = false;
+    for (int t = 1; t <= T; ++t) {
+        const bool vote = checked(t - 1);
+        S.msg_in = mb[(t - 1) & 1];
+        S.msg = mb[t & 1];
+        const bool bad = res_check_phase<true, Msg, kGeneric>(c, S, d1[(t - 1) & 1], d1[t & 1], PK,
+                                                              gw, NW);
+        if (vote && wave_ballot(bad) != 0ull && lane == 0) flags[(size_t)t * A.F + f] = 1;
+        ok &= team_barrier(ctr, (int)K * ++epoch);
+        if (vote && agent_load(flags + (size_t)t * A.F + f) == 0) {
+            // the decisions of iteration t - 1 satisfy H x = s: stop there
+            it = t - 1;
+            conv = 1;
+            stopped = true;
+            break;
+        }
+        res_group_sums<Msg>(c, S, part);
+        __syncthreads();
+        res_totals<Msg>(c, S, part);
+        __syncthreads();
+    }
+    if (!stopped) {
+        // the check of the last iteration (the channel decisions when T = 0)
+        const bool bad = res_check_phase<false, Msg, kGeneric>(c, S, d1[T & 1], nullptr, PK, gw, NW);
+        if (wave_ballot(bad) != 0ull && lane == 0) flags[(size_t)(T + 1) * A.F + f] = 1;
+        ok &= team_barrier(ctr, (int)K * ++epoch);
+        conv = agent_load(flags + (size_t)(T + 1) * A.F + f) == 0;
+    }
+
+    // Read-out over the frame's workgroups: decisions at the exit iteration
+    // (every workgroup holds the same totals).
+    const uint64_t *dexit = d1[it & 1];
+    uint8_t *bits_out = A.bits_out + (size_t)f * c.n;
+    for (unsigned v = gt; v < (unsigned)c.n; v += NT) {
+        const unsigned col = v / Z, jj = v - col * Z;
+        const int kind = c.col_kind[col];
+        const unsigned ref = (unsigned)c.col_ref[col];
+        int bit = llr[v] < 0.0f;
+        if (kind == COL_CORE) {
+            bit = tot[ref * Z + jj] < 0.0f;
+        } else if (kind == COL_DEG1 && it > 0) {
+            unsigned a = jj + Z - (unsigned)c.d1_shift[ref];
+            a -= (a >= Z) ? Z : 0u;
+            bit = (int)((dexit[ref * W + (a >> 6)] >> (a & 63u)) & 1ull);
+        }
+        bits_out[v] = (uint8_t)bit;
+    }
+    if (threadIdx.x == 0 && (k == 0 || !ok)) {
+        A.iters_out[f] = ok ? it : -1;  // -1: a barrier wait ran out
+        A.conv_out[f] = ok ? (uint8_t)conv : (uint8_t)0;
+    }
+}
+
+__global__ void split_clear(int32_t *p, unsigned n) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 }  // namespace
+
+bool split_offered(const CodeDev &c, bool fp16) {
+    return c.res_units > 0 && resident_layout(c, fp16).total <= kSplitMaxStateBytes;
+}
+
+// Workgroups per frame: up to kSplitMaxTeam while the frames' workgroups fit
+// one per CU of the 256.
+int split_team(int F) {
+    const int slots = 8 * ((F + 7) / 8);
+    int K = 256 / slots;
+    return K < 1 ? 1 : (K > kSplitMaxTeam ? kSplitMaxTeam : K);
+}
+
+hipError_t enqueue_split(const DecodeLaunch &l, const WorkLayout &W) {
+    const CodeDev &c = l.c;
+    if (W.split_frame == 0) return hipErrorInvalidValue;
+    const int K = split_team(l.F);
+    SplitArgs a{};
+    a.llr = l.llr;
+    a.syndrome = l.syndrome;
+    a.psi = reinterpret_cast<float *>(l.ws + W.psi);
+    a.msg[0] = l.ws + W.msg;
+    a.msg[1] = l.ws + W.split_msg;
+    a.synbits = reinterpret_cast<uint64_t *>(l.ws + W.synbits);
+    a.d1[0] = reinterpret_cast<uint64_t *>(l.ws + W.d1bits);
+    a.d1[1] = a.d1[0] + (size_t)l.F * W.d1bits_frame;
+    a.team = reinterpret_cast<int32_t *>(l.ws + W.team);
+    a.bits_out = l.bits_out;
+    a.iters_out = l.iters_out;
+    a.conv_out = l.conv_out;
+    a.msg_frame = W.split_frame;
+    a.psi_frame = W.psi_frame;
+    a.d1_frame = W.d1bits_frame;
+    a.syn_frame = W.synbits_frame;
+    a.T = l.T;
+    a.early_stop = l.early_stop;
+    a.check_from = l.check_from;
+    a.K = K;
+    a.F = l.F;
+    const size_t nt = (size_t)c.NC * c.Z * 4;
+    a.lds_q = (unsigned)nt;
+    a.lds_part = (unsigned)(2 * nt);
+    const size_t lds = (2 + kVnGroups) * nt;
+    const unsigned nclear = (unsigned)((size_t)l.F * (l.T + 3));
+    split_clear<<<dim3((nclear + 255) / 256), dim3(256), 0, l.stream>>>(a.team, nclear);
+    const dim3 grid((unsigned)(8 * K * ((l.F + 7) / 8))), block(kSplitThreads);
+    CodeDev cc = c;
+    void *args[] = {&cc, &a};
+    auto launch = [&](auto kernel) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), grid, block, args,
+                                          (unsigned)lds, l.stream);
+    };
+    const bool generic = c.n_large > 0;
+    if (l.fp16)
+        return generic ? launch(split_decode<_Float16, true>) : launch(split_decode<_Float16, false>);
+    return generic ? launch(split_decode<float, true>) : launch(split_decode<float, false>);
+}
 
 ResidentLayout resident_layout(const CodeDev &c, bool fp16) {
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };

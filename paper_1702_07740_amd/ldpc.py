@@ -32,8 +32,9 @@ EXPORTS = (
 )
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
-SCHEDULE_AUTO, SCHEDULE_LAUNCHES, SCHEDULE_RESIDENT = 0, 1, 2
-_SCHEDULES = {"auto": SCHEDULE_AUTO, "launches": SCHEDULE_LAUNCHES, "resident": SCHEDULE_RESIDENT}
+SCHEDULE_AUTO, SCHEDULE_LAUNCHES, SCHEDULE_RESIDENT, SCHEDULE_SPLIT = 0, 1, 2, 3
+_SCHEDULES = {"auto": SCHEDULE_AUTO, "launches": SCHEDULE_LAUNCHES, "resident": SCHEDULE_RESIDENT,
+              "split": SCHEDULE_SPLIT}
 
 
 class LdpcError(RuntimeError):
@@ -210,7 +211,8 @@ class Code:
         return ws[off:off + nbytes]
 
     def schedule(self, F=1, msg_fp16=False, want_llr=False, timing=False, schedule="auto") -> str:
-        """The schedule ("launches" or "resident") a decode of F frames with these options runs on."""
+        """The schedule ("launches", "resident" or "split") a decode of F frames with these
+        options runs on."""
         o = make_opts(msg_fp16=msg_fp16, schedule=schedule)
         if want_llr:
             o.llr_out = ctypes.c_void_p(1)  # only tested for null
@@ -220,7 +222,8 @@ class Code:
         out = ctypes.c_int32()
         _check(load().ldpc_decode_schedule(self._h, int(F), ctypes.byref(o), ctypes.byref(out)),
                "ldpc_decode_schedule")
-        return {SCHEDULE_LAUNCHES: "launches", SCHEDULE_RESIDENT: "resident"}[out.value]
+        return {SCHEDULE_LAUNCHES: "launches", SCHEDULE_RESIDENT: "resident",
+                SCHEDULE_SPLIT: "split"}[out.value]
 
     def decode(self, llr, syndrome, max_iters: int, early_stop=True, check_from_iter=0,
                msg_fp16=False, want_llr=False, workspace=None, out=None, stream=None,

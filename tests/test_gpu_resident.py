@@ -1,5 +1,6 @@
-"""The frame-resident schedule (one workgroup per frame, state in LDS) against
-the FP64 oracle and, bit for bit, against the per-iteration launches.
+"""The frame-resident schedule (one workgroup per frame, state in LDS) and the
+frame-split schedule (several co-resident workgroups per frame) against the
+FP64 oracle and, bit for bit, against the per-iteration launches.
 
 Every case prints its name, seed and shape before touching the GPU.
 """
@@ -37,12 +38,25 @@ def _run(g, Q, s, T, **kw):
     return bits.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy()
 
 
+def _split_offered(g, F, fp16):
+    from paper_1702_07740_amd import ldpc as mod
+    try:
+        return g.schedule(F=F, msg_fp16=fp16, schedule="split") == "split"
+    except mod.LdpcError:
+        return False
+
+
 def _same(g, Q, s, T, **kw):
-    """Decode on both schedules and require identical outputs."""
+    """Decode on every schedule offered for the batch and require identical
+    outputs: launches, resident, and frame-split where the batch allows it."""
     a = _run(g, Q, s, T, schedule="launches", **kw)
     b = _run(g, Q, s, T, schedule="resident", **kw)
     for name, u, v in zip(("bits", "iters", "converged"), a, b):
         assert np.array_equal(u, v), (name, kw)
+    if _split_offered(g, Q.shape[0], kw.get("msg_fp16", False)):
+        c = _run(g, Q, s, T, schedule="split", **kw)
+        for name, u, v in zip(("bits", "iters", "converged"), a, c):
+            assert np.array_equal(u, v), ("split", name, kw)
     return b
 
 
@@ -80,8 +94,18 @@ def test_schedule_selection(ldpc):
         big.schedule(schedule="resident")
     assert e.value.status == ldpc.LDPC_EUNSUPPORTED
     with pytest.raises(ldpc.LdpcError) as e:
-        small.schedule(schedule=3)
+        small.schedule(schedule=4)
     assert e.value.status == ldpc.LDPC_EINVAL
+    # the frame-split schedule: small codes, at most 256 frames
+    assert small.schedule(F=16, schedule="split") == "split"
+    assert small.schedule(F=256, msg_fp16=True, schedule="split") == "split"
+    for kw in (dict(F=257), dict(F=1, want_llr=True), dict(F=1, timing=True)):
+        with pytest.raises(ldpc.LdpcError) as e:
+            small.schedule(schedule="split", **kw)
+        assert e.value.status == ldpc.LDPC_EUNSUPPORTED
+    with pytest.raises(ldpc.LdpcError) as e:
+        big.schedule(F=1, schedule="split")
+    assert e.value.status == ldpc.LDPC_EUNSUPPORTED
     # a forced resident decode of a code whose state does not fit fails at
     # the call, before any launch
     Q = torch.zeros((1, big.n), dtype=torch.float32, device="cuda")
@@ -91,16 +115,17 @@ def test_schedule_selection(ldpc):
 
 
 # ---------------------------------------------------- oracle parity
+@pytest.mark.parametrize("schedule", ["resident", "split"])
 @pytest.mark.parametrize("snr,F,seed", [(-15.4, 16, 1), (-14.0, 16, 2), (-13.0, 16, 3)])
-def test_resident_parity_small_template(ldpc, oracle_mod, snr, F, seed):
+def test_resident_parity_small_template(ldpc, oracle_mod, snr, F, seed, schedule):
     """The n = 9600 template (Z = 64), 16 frames, max 100 iterations, early stop."""
     Z, T = 64, 100
     base = synth.template_base(144, Z, seed=1)
     g, o = ldpc.Code(base, Z), oracle_mod.OracleCode(base, Z)
     x, Q = synth.biawgn_frames(o.n, F, snr, seed=seed)
     s = o.syndrome(x)
-    _say("resident decode", "snr", snr, "F", F, "n", o.n)
-    bits, it, conv = _run(g, Q, s, T, schedule="resident")
+    _say(schedule, "decode", "snr", snr, "F", F, "n", o.n)
+    bits, it, conv = _run(g, Q, s, T, schedule=schedule)
     summ = check_decode_parity(o, Q, s, bits, it, conv, o.decode(Q, s, T, threads=8), T)
     print("summary", summ, flush=True)
 
@@ -172,11 +197,12 @@ def test_batch_independent(ldpc, oracle_mod):
     x, Q = synth.biawgn_frames(o.n, 6, -13.5, seed=61)
     s = o.syndrome(x)
     _say("resident batch independence")
-    full = _run(g, Q, s, 80, schedule="resident")
-    for f in (0, 3, 5):
-        alone = _run(g, Q[f:f + 1], s[f:f + 1], 80, schedule="resident")
-        for u, v in zip(alone, full):
-            assert np.array_equal(u[0], v[f])
+    for sch in ("resident", "split"):
+        full = _run(g, Q, s, 80, schedule=sch)
+        for f in (0, 3, 5):
+            alone = _run(g, Q[f:f + 1], s[f:f + 1], 80, schedule=sch)
+            for u, v in zip(alone, full):
+                assert np.array_equal(u[0], v[f])
 
 
 def test_many_frames(ldpc, oracle_mod):
