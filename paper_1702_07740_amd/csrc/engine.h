@@ -21,10 +21,12 @@ struct SlotDesc {
     uint64_t *d1b[2];
     uint64_t *synbits;
     int32_t *fail;
+    float *part;             // owner-group partial sums
     int F, T, early_stop, check_from;
     int start_step;          // engine step that runs this slot's iteration 1
     int slot_id, generation;
     int cn_tiles, vn_tiles;  // check-pass and variable-pass tiles per row / column
+    int g_tiles;             // check-pass tiles (256 positions) per owner group
 };
 
 struct Request {

@@ -45,8 +45,12 @@ struct SlotHead {
     const int32_t *tab;  // check pass: the code's row descriptors; variable pass: core_tab
     int32_t *fail;
     int32_t tiles;       // work tiles per row (check pass) or per core column (variable pass)
-    int32_t rows;        // mb (check pass) or NC (variable pass)
+    int32_t rows;        // check pass: rows with their own items; variable pass: NC
     int32_t start_step, T, F, stride;  // stride: core_tab_stride (variable pass)
+    // check pass, per frame: gitems owner-group items (gtiles per group) first,
+    // then rows x tiles row items; in the vote-only step gitems = 0 and every
+    // row has row items
+    int32_t gitems, gtiles;
 };
 
 // Work-item offsets by slot and the slot heads, in the kernel arguments.
@@ -78,11 +82,10 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
     const SlotHead &H = ix.head[s];
     const int t = step - H.start_step + 1;
     if (t < 1 || t > H.T + 1) return;
-    int local = item - ix.begin[s];
-    const unsigned tile = (unsigned)(local % H.tiles);
-    local /= H.tiles;
-    const int y = local % H.rows;  // row_list position (every row of an engine code is common)
-    const int f = local / H.rows;
+    const int local = item - ix.begin[s];
+    const int per_frame = H.gitems + H.rows * H.tiles;
+    const int f = local / per_frame;
+    const int r = local - f * per_frame;
     const bool vote_only = t == H.T + 1;
     const SlotDesc &S = slots[s];
     CnArgs A{};
@@ -98,6 +101,8 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
     A.d1_frame = S.L.d1bits_frame;
     A.syn_frame = S.L.synbits_frame;
     A.psi_frame = S.L.psi_frame;
+    A.part = S.part;
+    A.part_frame = S.L.part_frame;
     A.F = H.F;
     if (vote_only) {
         A.t = H.T;
@@ -117,6 +122,23 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
     // the row descriptor through the slot head (its address needs no slot load)
     CodeDev c = S.c;
     c.row_desc = H.tab;
+    if (r < H.gitems) {
+        // an owner group (never in the vote-only step)
+        const int g = r / H.gtiles;
+        const unsigned tile = (unsigned)(r - g * H.gtiles);
+        if (t == 1)
+            group_work<kFirst, Msg>(c, A, f, g, tile);
+        else
+            group_work<kSteady, Msg>(c, A, f, g, tile);
+        return;
+    }
+    const int r2 = r - H.gitems;
+    const int y0 = r2 / H.tiles;
+    const unsigned tile = (unsigned)(r2 - y0 * H.tiles);
+    // row_list position (every row of an engine code is common); outside the
+    // vote-only step the t-domain rows belong to the owner groups
+    const int lo = c.cls_end[kTdomClass - 1];
+    const int y = (vote_only || y0 < lo) ? y0 : y0 + c.n_tdom;
     if (vote_only)
         check_work_by_desc<Msg, kVoteOnly, CPT>(c, A, f, y, tile);
     else if (t == 1)
@@ -125,8 +147,9 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
         check_work_by_desc<Msg, kSteady, CPT>(c, A, f, y, tile);
 }
 
-// The variable pass over all slots (one variable per thread), with the batch
-// width of the largest column degree among them.
+// The variable pass over all slots (two variables per thread, reading the
+// owner-group partials the check pass wrote), with the batch width of the
+// largest column among them.
 template <typename Msg, int U>
 __global__ __launch_bounds__(kBlock) void engine_variable_pass(const SlotDesc *slots, SlotIndex ix,
                                                                int step) {
@@ -150,13 +173,15 @@ __global__ __launch_bounds__(kBlock) void engine_variable_pass(const SlotDesc *s
     V.fail = H.fail;
     V.msg_frame = S.L.msg_frame;
     V.tot_frame = S.L.tot_frame;
+    V.part = S.part;
+    V.part_frame = S.L.part_frame;
     V.F = H.F;
     V.t = t;
     // the column table through the slot head (its address needs no slot load)
     CodeDev c = S.c;
     c.core_tab = H.tab;
     c.core_tab_stride = H.stride;
-    variable_work<U, Msg, 1, false>(c, V, f, k, tile);
+    variable_work<U, Msg, vn_vpt<Msg>(), true>(c, V, f, k, tile);
 }
 
 template <typename Msg>
@@ -405,6 +430,7 @@ bool Engine::admit_one(const Request &rq, int s) {
     D.d1b[1] = D.d1b[0] + (size_t)rq.F * D.L.d1bits_frame;
     D.synbits = reinterpret_cast<uint64_t *>(ws + D.L.synbits);
     D.fail = reinterpret_cast<int32_t *>(ws + D.L.fail);
+    D.part = reinterpret_cast<float *>(ws + D.L.part);
     D.F = rq.F;
     D.T = rq.T;
     D.early_stop = early_stop ? 1 : 0;
@@ -413,7 +439,8 @@ bool Engine::admit_one(const Request &rq, int s) {
     D.slot_id = s;
     D.generation = sl.generation;
     D.cn_tiles = (int)check_tiles(rq.c.Z, cpt);
-    D.vn_tiles = (int)variable_tiles(rq.c.Z, 1);
+    D.vn_tiles = (int)variable_tiles(rq.c.Z, vn_vpt<float>());
+    D.g_tiles = (rq.c.Z + kBlock - 1) / kBlock;
 
     const CodeDev &c = rq.c;
     const int nfail = (rq.T + 1) * rq.F;
@@ -529,16 +556,22 @@ hipError_t Engine::step(int *active_out, int *queued_out) {
             const SlotDesc &D = slot[order[i]].desc;
             cn.begin[i] = cn_total;
             vn.begin[i] = vn_total;
-            cn.head[i] = SlotHead{D.c.row_desc, D.fail, D.cn_tiles, D.c.mb, D.start_step, D.T, D.F, 0};
+            // this step runs the slot's iteration t; t = T + 1 is its vote-only pass
+            const bool vote_only = step_no - D.start_step + 1 == D.T + 1;
+            const int gitems = vote_only ? 0 : D.c.n_groups * D.g_tiles;
+            const int rows = vote_only ? D.c.mb : D.c.mb - D.c.n_tdom;
+            cn.head[i] = SlotHead{D.c.row_desc, D.fail, D.cn_tiles, rows, D.start_step, D.T, D.F, 0,
+                                  gitems, D.g_tiles};
             vn.head[i] = SlotHead{D.c.core_tab, D.fail, D.vn_tiles, D.c.NC, D.start_step, D.T, D.F,
-                                  D.c.core_tab_stride};
-            cn_total += D.cn_tiles * D.c.mb * D.F;
+                                  D.c.core_tab_stride, 0, 1};
+            cn_total += (gitems + D.cn_tiles * rows) * D.F;
             vn_total += D.vn_tiles * D.c.NC * D.F;
         }
         cn.begin[n] = cn_total;
         vn.begin[n] = vn_total;
-        int max_deg = 0;
-        for (int i = 0; i < n; ++i) max_deg = std::max(max_deg, slot[order[i]].desc.c.max_core_deg);
+        int max_deg = 0;  // twice the largest half of a column's terms (the batch width)
+        for (int i = 0; i < n; ++i)
+            max_deg = std::max(max_deg, 2 * slot[order[i]].desc.c.max_half_terms);
         // 5. one iteration of every active slot, then the status copy
         const dim3 gc(xcd_grid((unsigned)cn_total)), gv(xcd_grid((unsigned)vn_total)), b(kBlock);
         if (fp16) {
