@@ -302,7 +302,7 @@ __device__ __forceinline__ bool res_check_phase(const CodeDev &c, const ResView<
 // group), into part[g].
 template <typename Msg>
 __device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<Msg> &S,
-                                               float *const (&part)[kVnGroups]) {
+                                               float *const *part) {
     const unsigned nw = blockDim.x >> 6;
     const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned Z = S.Z, units = (unsigned)c.NC * S.W * kVnGroups;
@@ -318,8 +318,8 @@ __device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<M
         const int deg = uniform_i32(c.core_deg + k);
         const int own = uniform_i32(c.core_own + k), ng = uniform_i32(c.core_ngrp + k);
         const int terms = ng + deg - own;
-        const int half = (terms + 1) / 2;
-        const int t0 = g * half, t1 = min(terms, t0 + half);
+        const int per = (terms + kVnGroups - 1) / kVnGroups;
+        const int t0 = g * per, t1 = min(terms, t0 + per);
         const int32_t *tab = c.res_core + (size_t)k * c.res_core_stride;
         // The column's (offset, shift) pairs, 64 at a time, one per lane
         // (one vector load instead of a chain of scalar loads); a block's
@@ -373,7 +373,7 @@ __device__ __forceinline__ void res_group_sums(const CodeDev &c, const ResView<M
 // Variable phase, second half (after a barrier): L_v = (Q_v log2(e) + S0) + S1.
 template <typename Msg>
 __device__ __forceinline__ void res_totals(const CodeDev &c, const ResView<Msg> &S,
-                                           float *const (&part)[kVnGroups]) {
+                                           float *const *part) {
     const unsigned n = (unsigned)c.NC * S.Z;
     for (unsigned i = threadIdx.x; i < n; i += blockDim.x) {
         float ps[kVnGroups];
@@ -397,8 +397,10 @@ __global__ __launch_bounds__(kResThreads) void resident_decode(CodeDev c, Reside
     S.tot = reinterpret_cast<float *>(lds + A.lds_tot);
     float *qc = reinterpret_cast<float *>(lds + A.lds_q);
     S.q = qc;
-    float *const part[kVnGroups] = {reinterpret_cast<float *>(lds + A.lds_part),
-                                    reinterpret_cast<float *>(lds + A.lds_part) + c.NC * c.Z};
+    float *part[kVnGroups];  // the row-group sums, NC * Z each
+#pragma unroll
+    for (int g = 0; g < kVnGroups; ++g)
+        part[g] = reinterpret_cast<float *>(lds + A.lds_part) + (size_t)g * c.NC * c.Z;
     uint64_t *syn = reinterpret_cast<uint64_t *>(lds + A.lds_syn);
     S.syn = syn;
     uint64_t *d1 = reinterpret_cast<uint64_t *>(lds + A.lds_d1);  // [2][ND1][W]
@@ -588,8 +590,10 @@ __global__ __launch_bounds__(kSplitThreads) void split_decode(CodeDev c, SplitAr
     const PhiConsts PK = phi_consts();
     float *tot = reinterpret_cast<float *>(lds);
     float *qc = reinterpret_cast<float *>(lds + A.lds_q);
-    float *const part[kVnGroups] = {reinterpret_cast<float *>(lds + A.lds_part),
-                                    reinterpret_cast<float *>(lds + A.lds_part) + c.NC * c.Z};
+    float *part[kVnGroups];  // the row-group sums, NC * Z each
+#pragma unroll
+    for (int g = 0; g < kVnGroups; ++g)
+        part[g] = reinterpret_cast<float *>(lds + A.lds_part) + (size_t)g * c.NC * c.Z;
     Msg *mb[2] = {reinterpret_cast<Msg *>(A.msg[0]) + (size_t)f * A.msg_frame,
                   reinterpret_cast<Msg *>(A.msg[1]) + (size_t)f * A.msg_frame};
     uint64_t *d1[2] = {A.d1[0] + (size_t)f * A.d1_frame, A.d1[1] + (size_t)f * A.d1_frame};
