@@ -32,28 +32,28 @@ METRIC = "raw decoded Mbit/s, n=1e6 R=0.02, 100 iters; p99 latency; FP16 vs FP32
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 PAPER_KRAW_MBPS = 1.72       # GTX 1080, q=21 QC code, Table II (context only)
 
-# HBM traffic of the steady check pass per launch of F frames of this
-# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch), each scaled by what the counter reads for a 1 GiB device copy
-# (FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB: factors 2.0 and 1.0).  It holds
-# only for the kernel sources it was taken on; any change to them makes the
-# fingerprint differ and the figure is reported as null.
+# HBM traffic of the steady check pass per frame, at 8 frames (cache-resident)
+# and 32 frames (HBM-resident), from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch, divided by the dispatch's frames: a decode of
+# F frames without per-pass events runs two dispatches of F/2 frames per pass,
+# one per stream), each scaled by what the counter reads for a 1 GiB device
+# copy (FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB: factors 2.0 and 1.0).  The
+# figures hold only for the kernel sources they were taken on; any change to
+# them makes the fingerprint differ and they are reported as null.
 KERNEL_SOURCES = ("internal.h", "passes.h", "decoder.hip")
-MEASURED_SOURCES = "25c266145e979e7d"
+MEASURED_SOURCES = "8270247759b96173"
 MEASURED_TRAFFIC = {
-    "check_pass_F8": {"fetch_kib": 51070.5, "write_kib": 66049.3, "fetch_scale": 2.0,
+    "check_pass_F8": {"fetch_kib": 6518.0, "write_kib": 8252.0, "fetch_scale": 2.0,
                       "write_scale": 1.0},
-    "check_pass_F32": {"fetch_kib": 206034.3, "write_kib": 264351.0, "fetch_scale": 2.0,
+    "check_pass_F32": {"fetch_kib": 6421.9, "write_kib": 8260.2, "fetch_scale": 2.0,
                        "write_scale": 1.0},
 }
 # Instruction counts of the steady check pass per frame (rocprofv3 --pmc
-# SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32, SQ_INSTS_SALU per 8-frame dispatch,
-# divided by 8): wave64 instructions, transcendentals included in VALU.
+# SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32, SQ_INSTS_SALU per dispatch, divided by
+# the dispatch's frames): wave64 instructions, transcendentals included in VALU.
 MEASURED_ISSUE = {
-    "check_pass_fp32": {"valu": 7.138e6 / 8, "trans": 0.800e6 / 8,
-                        "salu": 2.950e6 / 8},
-    "check_pass_fp16": {"valu": 7.783e6 / 8, "trans": 0.800e6 / 8,
-                        "salu": 3.020e6 / 8},
+    "check_pass_fp32": {"valu": 892396, "trans": 100008, "salu": 368843},
+    "check_pass_fp16": {"valu": 972961, "trans": 100008, "salu": 377555},
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, each issuing one wave64 VALU
 # instruction every 4 cycles, at 2.4 GHz = 614.4 G wave-instructions/s.  A
@@ -73,12 +73,12 @@ def kernel_fingerprint() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the counters, or None if stale."""
-    m = MEASURED_TRAFFIC.get(kernel)
+def measured_traffic(kernel: str, F: int):
+    """HBM bytes of `kernel` for F frames from the counters, or None if stale."""
+    m = MEASURED_TRAFFIC.get(f"{kernel}_F{F}")
     if m is None or MEASURED_SOURCES != kernel_fingerprint():
         return None
-    return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+    return F * 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
 
 def issue_ceiling(kernel: str, F: int, avg_ms: float):
@@ -228,7 +228,7 @@ def roofline_entry(kr, F, where, fp16=False):
     ent = {"bound": "hbm", "kernel": dom, "achieved": round(k["achieved_GBs"], 1),
            "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(k["achieved_GBs"] / HBM_PEAK_GBS, 4),
-           "traffic": None if fp16 else measured_traffic(f"{dom}_F{F}"),
+           "traffic": None if fp16 else measured_traffic(dom, F),
            "algorithmic_bytes": k["bytes_per_launch"], "avg_ms": k["avg_ms"],
            "hbm_min_ms": hbm_ms, "issue": iss, "working_set": where, "kernels": kr}
     if iss is not None and iss["min_ms"] > hbm_ms:

@@ -21,6 +21,11 @@ struct ldpc_code {
     size_t lds_limit;       // LDS bytes one workgroup may take on that device
     CodeDev dev;            // sizes + device table pointers
     int32_t *table;         // one device allocation holding every table
+    // the second stream of two-stream decodes, its fork and join events, and
+    // the lock that keeps one call's record / wait pairs together
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    std::mutex aux_lock;
 };
 
 namespace {
@@ -434,6 +439,16 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         return fail_with(LDPC_EDEVICE, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
     }
     code->lds_limit = lds > 0 ? (size_t)lds : 0;
+    // the second stream (default priority) and its events; without them every
+    // decode runs on the caller's stream alone
+    if (hipStreamCreateWithFlags(&code->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&code->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&code->join, hipEventDisableTiming) != hipSuccess) {
+        if (code->fork) (void)hipEventDestroy(code->fork);
+        if (code->aux) (void)hipStreamDestroy(code->aux);
+        code->aux = nullptr;
+        code->fork = code->join = nullptr;
+    }
     // set-up of the no-allocation decode on this device (its failure is
     // reported by ldpc_decode_batch_noalloc, which retries the lookup)
     (void)scratch_setup(code->device);
@@ -527,6 +542,10 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
 
 void ldpc_code_destroy(ldpc_code *code) {
     if (!code) return;
+    if (code->aux) (void)hipStreamSynchronize(code->aux);
+    if (code->join) (void)hipEventDestroy(code->join);
+    if (code->fork) (void)hipEventDestroy(code->fork);
+    if (code->aux) (void)hipStreamDestroy(code->aux);
     if (code->table) (void)hipFree(code->table);
     delete code;
 }
@@ -543,7 +562,8 @@ size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
     ldpc_decode_opts o;
     ldpc_decode_opts_init(&o);
     if (opts) o = *opts;
-    return ldpc::work_layout(code->dev, F, max_iters, o.msg_fp16 != 0, o.llr_out != nullptr).total;
+    return ldpc::decode_workspace_bytes(code->dev, F, max_iters, o.msg_fp16 != 0,
+                                        o.llr_out != nullptr);
 }
 
 }  // extern "C"
@@ -658,8 +678,8 @@ int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const 
                          o.n_timing_events, 4ll * max_iters);
     if ((int64_t)(max_iters + 1) * F >= (1ll << 31))
         return fail_with(LDPC_EINVAL, "(max_iters + 1) * F too large");
-    const size_t need = ldpc::work_layout(code->dev, F, max_iters, o.msg_fp16 != 0,
-                                          o.llr_out != nullptr).total;
+    const size_t need = ldpc::decode_workspace_bytes(code->dev, F, max_iters, o.msg_fp16 != 0,
+                                                     o.llr_out != nullptr);
     if (noalloc) {
         if (need > kScratchBytes)
             return fail_with(LDPC_EWORKSPACE,
@@ -705,9 +725,19 @@ int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const 
     l.events = reinterpret_cast<hipEvent_t *>(o.timing_events);
     l.stream = static_cast<hipStream_t>(stream);
     const ldpc::WorkLayout WL = ldpc::work_layout(l.c, F, max_iters, l.fp16 != 0, false);
-    hipError_t e = sched == LDPC_SCHEDULE_RESIDENT ? ldpc::enqueue_resident(l, WL, code->lds_limit)
-                   : sched == LDPC_SCHEDULE_SPLIT  ? ldpc::enqueue_split(l, WL)
-                                                   : ldpc::enqueue_decode(l);
+    hipError_t e;
+    if (sched == LDPC_SCHEDULE_RESIDENT) {
+        e = ldpc::enqueue_resident(l, WL, code->lds_limit);
+    } else if (sched == LDPC_SCHEDULE_SPLIT) {
+        e = ldpc::enqueue_split(l, WL);
+    } else {
+        ldpc_code *mc = const_cast<ldpc_code *>(code);
+        std::lock_guard<std::mutex> g(mc->aux_lock);
+        l.aux = mc->aux;
+        l.fork = mc->fork;
+        l.join = mc->join;
+        e = ldpc::enqueue_decode(l);
+    }
     if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
     return LDPC_OK;
 }

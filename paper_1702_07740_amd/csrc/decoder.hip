@@ -36,6 +36,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 namespace ldpc {
 
 namespace {
@@ -254,65 +256,82 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(CodeDev c, const uint8
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline unsigned tiles(int n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// The kernel sequence of one decode, in three parts so that two decodes can
+// be interleaved launch by launch on two streams: set-up, one iteration
+// (check pass and variable pass), and the final vote and read-out.
 template <typename Msg>
-hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
-    const CodeDev &c = l.c;
-    const int F = l.F, T = l.T;
-    char *ws = l.ws;
-    void *msg = ws + L.msg;
-    float *tot = reinterpret_cast<float *>(ws + L.tot);
-    float *psi = reinterpret_cast<float *>(ws + L.psi);
-    uint64_t *d1b[2] = {reinterpret_cast<uint64_t *>(ws + L.d1bits),
-                        reinterpret_cast<uint64_t *>(ws + L.d1bits) + (size_t)F * L.d1bits_frame};
-    uint64_t *synbits = reinterpret_cast<uint64_t *>(ws + L.synbits);
-    int32_t *fail = reinterpret_cast<int32_t *>(ws + L.fail);
-    float *d1p[2] = {nullptr, nullptr};
-    if (l.llr_out) {
-        d1p[0] = reinterpret_cast<float *>(ws + L.d1post);
-        d1p[1] = d1p[0] + (size_t)F * L.psi_frame;
-    }
-    hipStream_t st = l.stream;
-
-    const int nfail = (T + 1) * F;
-    init_fail<<<dim3((nfail + kBlock - 1) / kBlock), dim3(kBlock), 0, st>>>(fail, F, T, l.early_stop,
-                                                                           l.check_from);
-    pack_syndrome<<<dim3(tiles(c.Z), c.mb, F), dim3(kBlock), 0, st>>>(c, l.syndrome, synbits,
-                                                                     L.synbits_frame);
-    if (c.NC > 0)
-        init_totals<<<dim3(tiles(c.Z), c.NC, F), dim3(kBlock), 0, st>>>(c, l.llr, tot, L.tot_frame);
-    if (c.ND1 > 0)
-        init_psi<<<dim3(tiles(c.Z), c.ND1, F), dim3(kBlock), 0, st>>>(c, l.llr, psi, L.psi_frame);
-
-    auto checked = [&](int t) { return t == T || (l.early_stop && t >= l.check_from); };
-
+struct Sequence {
+    const DecodeLaunch &l;
+    WorkLayout L;
     CnArgs a{};
-    a.llr = l.llr;
-    a.psi = psi;
-    a.msg = msg;
-    a.tot = tot;
-    a.synbits = synbits;
-    a.fail = fail;
-    a.msg_frame = L.msg_frame;
-    a.tot_frame = L.tot_frame;
-    a.d1_frame = L.d1bits_frame;
-    a.syn_frame = L.synbits_frame;
-    a.psi_frame = L.psi_frame;
-    a.part = reinterpret_cast<float *>(ws + L.part);
-    a.part_frame = L.part_frame;
-    a.F = F;
-
     VnArgs v{};
-    v.llr = l.llr;
-    v.msg = msg;
-    v.tot = tot;
-    v.fail = fail;
-    v.msg_frame = L.msg_frame;
-    v.tot_frame = L.tot_frame;
-    v.part = reinterpret_cast<const float *>(ws + L.part);
-    v.part_frame = L.part_frame;
-    v.F = F;
+    uint64_t *d1b[2];
+    float *d1p[2] = {nullptr, nullptr};
+    int32_t *fail;
+    float *tot, *psi;
+    uint64_t *synbits;
 
-    for (int t = 1; t <= T; ++t) {
+    Sequence(const DecodeLaunch &launch, const WorkLayout &layout) : l(launch), L(layout) {
+        const int F = l.F;
+        char *ws = l.ws;
+        tot = reinterpret_cast<float *>(ws + L.tot);
+        psi = reinterpret_cast<float *>(ws + L.psi);
+        synbits = reinterpret_cast<uint64_t *>(ws + L.synbits);
+        d1b[0] = reinterpret_cast<uint64_t *>(ws + L.d1bits);
+        d1b[1] = d1b[0] + (size_t)F * L.d1bits_frame;
+        fail = reinterpret_cast<int32_t *>(ws + L.fail);
+        if (l.llr_out) {
+            d1p[0] = reinterpret_cast<float *>(ws + L.d1post);
+            d1p[1] = d1p[0] + (size_t)F * L.psi_frame;
+        }
+        a.llr = l.llr;
+        a.psi = psi;
+        a.msg = ws + L.msg;
+        a.tot = tot;
+        a.synbits = synbits;
+        a.fail = fail;
+        a.msg_frame = L.msg_frame;
+        a.tot_frame = L.tot_frame;
+        a.d1_frame = L.d1bits_frame;
+        a.syn_frame = L.synbits_frame;
+        a.psi_frame = L.psi_frame;
+        a.part = reinterpret_cast<float *>(ws + L.part);
+        a.part_frame = L.part_frame;
+        a.F = F;
+        v.llr = l.llr;
+        v.msg = a.msg;
+        v.tot = tot;
+        v.fail = fail;
+        v.msg_frame = L.msg_frame;
+        v.tot_frame = L.tot_frame;
+        v.part = a.part;
+        v.part_frame = L.part_frame;
+        v.F = F;
+    }
+
+    bool checked(int t) const { return t == l.T || (l.early_stop && t >= l.check_from); }
+
+    void setup() {
+        const CodeDev &c = l.c;
+        const int F = l.F;
+        hipStream_t st = l.stream;
+        const int nfail = (l.T + 1) * F;
+        init_fail<<<dim3((nfail + kBlock - 1) / kBlock), dim3(kBlock), 0, st>>>(fail, F, l.T,
+                                                                               l.early_stop,
+                                                                               l.check_from);
+        pack_syndrome<<<dim3(tiles(c.Z), c.mb, F), dim3(kBlock), 0, st>>>(c, l.syndrome, synbits,
+                                                                         L.synbits_frame);
+        if (c.NC > 0)
+            init_totals<<<dim3(tiles(c.Z), c.NC, F), dim3(kBlock), 0, st>>>(c, l.llr, tot,
+                                                                           L.tot_frame);
+        if (c.ND1 > 0)
+            init_psi<<<dim3(tiles(c.Z), c.ND1, F), dim3(kBlock), 0, st>>>(c, l.llr, psi,
+                                                                         L.psi_frame);
+    }
+
+    void iteration(int t) {
+        const CodeDev &c = l.c;
+        hipStream_t st = l.stream;
         a.t = t;
         a.vote = checked(t - 1) ? 1 : 0;
         a.d1_from_llr = (t == 1);
@@ -324,52 +343,84 @@ hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
         hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
         if (t == 1) {
             if (a.d1post)
-                launch_check_pass<Msg, kFirst | kPost>(c, a, F, l.cpt, st, e0, e1);
+                launch_check_pass<Msg, kFirst | kPost>(c, a, l.F, l.cpt, st, e0, e1);
             else
-                launch_check_pass<Msg, kFirst>(c, a, F, l.cpt, st, e0, e1);
+                launch_check_pass<Msg, kFirst>(c, a, l.F, l.cpt, st, e0, e1);
         } else {
             if (a.d1post)
-                launch_check_pass<Msg, kSteady | kPost>(c, a, F, l.cpt, st, e0, e1);
+                launch_check_pass<Msg, kSteady | kPost>(c, a, l.F, l.cpt, st, e0, e1);
             else
-                launch_check_pass<Msg, kSteady>(c, a, F, l.cpt, st, e0, e1);
+                launch_check_pass<Msg, kSteady>(c, a, l.F, l.cpt, st, e0, e1);
         }
         if (c.NC > 0) {
             v.t = t;
-            launch_variable_pass<Msg>(c, v, F, st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+            launch_variable_pass<Msg>(c, v, l.F, st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
         } else if (ev) {
             (void)hipEventRecord(ev[2], st);
             (void)hipEventRecord(ev[3], st);
         }
     }
-    // the check of the last iteration (or of the channel decisions when T = 0)
-    a.t = T;
-    a.vote = 1;
-    a.d1_from_llr = (T == 0);
-    a.d1_prev = d1b[T & 1];
-    a.d1_cur = nullptr;
-    a.d1post = nullptr;
-    a.skip_after = T >= 1 ? T - 1 : -1;
-    launch_check_pass<Msg, kVoteOnly>(c, a, F, l.cpt, st);
 
-    FinArgs fa{};
-    fa.llr = l.llr;
-    fa.tot = tot;
-    fa.d1bits[0] = d1b[0];
-    fa.d1bits[1] = d1b[1];
-    fa.d1post[0] = d1p[0];
-    fa.d1post[1] = d1p[1];
-    fa.fail = fail;
-    fa.bits_out = l.bits_out;
-    fa.iters_out = l.iters_out;
-    fa.conv_out = l.conv_out;
-    fa.llr_out = l.llr_out;
-    fa.tot_frame = L.tot_frame;
-    fa.d1_frame = L.d1bits_frame;
-    fa.psi_frame = L.psi_frame;
-    fa.F = F;
-    fa.T = T;
-    frame_exit<<<dim3(F), dim3(64), 0, st>>>(fa);
-    finalize<<<dim3(tiles(c.n), F), dim3(kBlock), 0, st>>>(c, fa);
+    void finish() {
+        const CodeDev &c = l.c;
+        const int F = l.F, T = l.T;
+        hipStream_t st = l.stream;
+        // the check of the last iteration (or of the channel decisions when T = 0)
+        a.t = T;
+        a.vote = 1;
+        a.d1_from_llr = (T == 0);
+        a.d1_prev = d1b[T & 1];
+        a.d1_cur = nullptr;
+        a.d1post = nullptr;
+        a.skip_after = T >= 1 ? T - 1 : -1;
+        launch_check_pass<Msg, kVoteOnly>(c, a, F, l.cpt, st);
+
+        FinArgs fa{};
+        fa.llr = l.llr;
+        fa.tot = tot;
+        fa.d1bits[0] = d1b[0];
+        fa.d1bits[1] = d1b[1];
+        fa.d1post[0] = d1p[0];
+        fa.d1post[1] = d1p[1];
+        fa.fail = fail;
+        fa.bits_out = l.bits_out;
+        fa.iters_out = l.iters_out;
+        fa.conv_out = l.conv_out;
+        fa.llr_out = l.llr_out;
+        fa.tot_frame = L.tot_frame;
+        fa.d1_frame = L.d1bits_frame;
+        fa.psi_frame = L.psi_frame;
+        fa.F = F;
+        fa.T = T;
+        frame_exit<<<dim3(F), dim3(64), 0, st>>>(fa);
+        finalize<<<dim3(tiles(c.n), F), dim3(kBlock), 0, st>>>(c, fa);
+    }
+};
+
+// One decode on one stream, or the two halves of the frames on the caller's
+// stream and the library's second stream, launch by launch in turn, so that
+// each half's kernels fill the other's gaps between dependent passes.
+template <typename Msg>
+hipError_t enqueue_typed(const DecodeLaunch &l, const WorkLayout &L) {
+    Sequence<Msg> s(l, L);
+    s.setup();
+    for (int t = 1; t <= l.T; ++t) s.iteration(t);
+    s.finish();
+    return hipGetLastError();
+}
+
+template <typename Msg>
+hipError_t enqueue_pair(const DecodeLaunch &la, const WorkLayout &La, const DecodeLaunch &lb,
+                        const WorkLayout &Lb) {
+    Sequence<Msg> sa(la, La), sb(lb, Lb);
+    sa.setup();
+    sb.setup();
+    for (int t = 1; t <= la.T; ++t) {
+        sa.iteration(t);
+        sb.iteration(t);
+    }
+    sa.finish();
+    sb.finish();
     return hipGetLastError();
 }
 
@@ -410,7 +461,43 @@ WorkLayout work_layout(const CodeDev &c, int F, int T, bool fp16, bool want_llr)
     return L;
 }
 
+// Frames of the first half when a decode runs on two streams.
+static int first_half(int F) { return (F + 1) / 2; }
+
+size_t decode_workspace_bytes(const CodeDev &c, int F, int T, bool fp16, bool want_llr) {
+    const size_t one = work_layout(c, F, T, fp16, want_llr).total;
+    if (F < 2) return one;
+    const int F1 = first_half(F);
+    const size_t two = work_layout(c, F1, T, fp16, want_llr).total +
+                       work_layout(c, F - F1, T, fp16, want_llr).total;
+    return std::max(one, two);
+}
+
 hipError_t enqueue_decode(const DecodeLaunch &l) {
+    if (l.F >= 2 && !l.events && l.aux && l.fork && l.join) {
+        const bool fp16 = l.fp16 != 0, llr = l.llr_out != nullptr;
+        const int F1 = first_half(l.F);
+        DecodeLaunch a = l, b = l;
+        a.F = F1;
+        b.F = l.F - F1;
+        const WorkLayout La = work_layout(l.c, a.F, l.T, fp16, llr);
+        const WorkLayout Lb = work_layout(l.c, b.F, l.T, fp16, llr);
+        b.llr = l.llr + (size_t)F1 * l.c.n;
+        b.syndrome = l.syndrome + (size_t)F1 * l.c.m;
+        b.bits_out = l.bits_out + (size_t)F1 * l.c.n;
+        b.iters_out = l.iters_out + F1;
+        b.conv_out = l.conv_out + F1;
+        b.llr_out = l.llr_out ? l.llr_out + (size_t)F1 * l.c.n : nullptr;
+        b.ws = l.ws + La.total;
+        b.stream = l.aux;
+        hipError_t e = hipEventRecord(l.fork, l.stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(l.aux, l.fork, 0);
+        if (e != hipSuccess) return e;
+        e = fp16 ? enqueue_pair<_Float16>(a, La, b, Lb) : enqueue_pair<float>(a, La, b, Lb);
+        if (e == hipSuccess) e = hipEventRecord(l.join, l.aux);
+        if (e == hipSuccess) e = hipStreamWaitEvent(l.stream, l.join, 0);
+        return e;
+    }
     const WorkLayout L = work_layout(l.c, l.F, l.T, l.fp16 != 0, l.llr_out != nullptr);
     return l.fp16 ? enqueue_typed<_Float16>(l, L) : enqueue_typed<float>(l, L);
 }

@@ -196,11 +196,19 @@ struct DecodeLaunch {
     char *ws;
     hipEvent_t *events;    // optional: 4T caller events, start and end of each iteration kernel
     hipStream_t stream;
+    // the library's second stream and its fork / join events: the per-iteration
+    // launches of F >= 2 frames (without caller events) run the two halves of the
+    // frames on `stream` and `aux`, joined back into `stream` (null: one stream)
+    hipStream_t aux;
+    hipEvent_t fork, join;
 };
 
 // Enqueue the whole decode on l.stream.  Returns hipSuccess or the first
 // launch error.
 hipError_t enqueue_decode(const DecodeLaunch &l);
+// Workspace bytes of a decode on any schedule (the two-stream split of the
+// launches takes two independent layouts of half the frames each).
+size_t decode_workspace_bytes(const CodeDev &c, int F, int T, bool fp16, bool want_llr);
 
 // Frame-resident schedule (resident.hip): one workgroup per frame runs every
 // iteration with the frame's state in LDS.  Byte offsets of that state:
