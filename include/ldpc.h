@@ -161,7 +161,7 @@ void ldpc_decode_opts_init(ldpc_decode_opts *opts);
  * ldpc_decode_batch runs for F frames with these options (NULL = defaults).
  *   schedule_out  host
  * Errors: LDPC_EINVAL (null, F outside [1, 65535], schedule out of range),
- * LDPC_EUNSUPPORTED (RESIDENT requested where it is not possible). */
+ * LDPC_EUNSUPPORTED (RESIDENT or SPLIT requested where it is not possible). */
 int ldpc_decode_schedule(const ldpc_code *code, int32_t F, const ldpc_decode_opts *opts,
                          int32_t *schedule_out);
 
@@ -186,7 +186,12 @@ size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
  *   stream     hipStream_t or NULL
  * Messages are clamped through the Phi argument range [1e-7, 30].  Frames are
  * independent: frame f's outputs depend only on frame f's inputs, bit for bit,
- * whatever F and the other frames are.
+ * whatever F and the other frames are.  On the per-iteration launches, F >= 2
+ * frames without timing_events run as two halves, the second on a stream the
+ * code handle owns, forked from and joined back into `stream` by events: the
+ * decode stays ordered on `stream` like any other work there (and can be
+ * captured into a graph from it); calls with one code handle from several host
+ * threads are safe, and their second halves share that stream.
  * Errors: LDPC_EINVAL (F < 1, max_iters < 0, check_from_iter < 0, null
  * pointer, checks_per_thread not 0/1/2/4, schedule out of range, too few
  * timing events), LDPC_EUNSUPPORTED (RESIDENT requested where it is not
