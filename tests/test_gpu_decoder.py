@@ -349,6 +349,27 @@ def test_timing_events(ldpc, oracle_mod):
     ev.close()
 
 
+@pytest.mark.parametrize("Z,F", [(64, 5), (1000, 3)])
+def test_two_streams_match_one(ldpc, oracle_mod, Z, F):
+    """Without per-pass events the launches run the frames in two halves on
+    two streams (here 3 + 2 and 2 + 1 frames); with events they run on one.
+    Bits, iteration counts, flags and posteriors agree exactly, FP32 and FP16."""
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    x, Q = synth.biawgn_frames(g.n, F, -13.5, seed=50 + F)
+    s = oracle_mod.OracleCode(base, Z).syndrome(x)
+    T = 30
+    _say("two streams vs one", Z, F)
+    for fp16 in (False, True):
+        two = _gpu_decode(g, Q, s, T, msg_fp16=fp16, want_llr=True, schedule="launches")
+        ev = _HipEvents(4 * T)
+        one = _gpu_decode(g, Q, s, T, msg_fp16=fp16, want_llr=True, schedule="launches",
+                          timing_events=ev.arr)
+        ev.close()
+        for name, a, b in zip(("bits", "iters", "converged", "llr"), two, one):
+            assert np.array_equal(a, b), (name, fp16)
+
+
 @pytest.mark.parametrize("schedule", ["launches", "resident"])
 def test_decode_replays_from_a_captured_graph(ldpc, oracle_mod, schedule):
     """A whole decode (caller-owned workspace and outputs) captured by stream
