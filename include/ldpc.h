@@ -84,7 +84,7 @@ typedef struct {
  * them to the current HIP device, to which the handle is bound.
  * Errors: LDPC_EINVAL (shape, shift range, null), LDPC_EUNSUPPORTED (a row of
  * degree > LDPC_MAX_ROW_DEGREE, a row with no block, or more than 65535 base
- * rows or columns of degree >= 2), LDPC_ENOMEM, LDPC_EDEVICE.
+ * rows or base columns), LDPC_ENOMEM, LDPC_EDEVICE.
  */
 int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldpc_code **out);
 

@@ -226,8 +226,8 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         if (d > maxdeg) maxdeg = d;
     }
     const int NS = (int)st_row.size(), NC = (int)core_col.size(), ND1 = (int)d1_col.size();
-    if (mb > 65535 || NC > 65535)  // base rows and core columns index grid.y
-        return fail_with(LDPC_EUNSUPPORTED, "more than 65535 base rows or core columns");
+    if (mb > 65535 || nb > 65535)  // base rows and base columns index grid.y
+        return fail_with(LDPC_EUNSUPPORTED, "more than 65535 base rows or base columns");
     {
         // every per-frame array is addressed with 32-bit byte offsets
         const int64_t lim = (1ll << 30) - ldpc::kLanePad;

@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void init_psi(CodeDev c, const float *llr, 
 __global__ __launch_bounds__(64) void frame_exit(FinArgs A) { frame_exit_work(A, blockIdx.x); }
 
 __global__ __launch_bounds__(kBlock) void finalize(CodeDev c, FinArgs A) {
-    finalize_work(c, A, blockIdx.y, blockIdx.x);
+    finalize_work(c, A, blockIdx.z, blockIdx.y, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void syndrome_kernel(CodeDev c, const uint8_t *bits,
@@ -319,13 +319,13 @@ struct Sequence {
         init_fail<<<dim3((nfail + kBlock - 1) / kBlock), dim3(kBlock), 0, st>>>(fail, F, l.T,
                                                                                l.early_stop,
                                                                                l.check_from);
-        pack_syndrome<<<dim3(tiles(c.Z), c.mb, F), dim3(kBlock), 0, st>>>(c, l.syndrome, synbits,
+        pack_syndrome<<<dim3(setup_tiles(c.Z), c.mb, F), dim3(kBlock), 0, st>>>(c, l.syndrome, synbits,
                                                                          L.synbits_frame);
         if (c.NC > 0)
-            init_totals<<<dim3(tiles(c.Z), c.NC, F), dim3(kBlock), 0, st>>>(c, l.llr, tot,
+            init_totals<<<dim3(setup_tiles(c.Z), c.NC, F), dim3(kBlock), 0, st>>>(c, l.llr, tot,
                                                                            L.tot_frame);
         if (c.ND1 > 0)
-            init_psi<<<dim3(tiles(c.Z), c.ND1, F), dim3(kBlock), 0, st>>>(c, l.llr, psi,
+            init_psi<<<dim3(setup_tiles(c.Z), c.ND1, F), dim3(kBlock), 0, st>>>(c, l.llr, psi,
                                                                          L.psi_frame);
     }
 
@@ -393,7 +393,7 @@ struct Sequence {
         fa.F = F;
         fa.T = T;
         frame_exit<<<dim3(F), dim3(64), 0, st>>>(fa);
-        finalize<<<dim3(tiles(c.n), F), dim3(kBlock), 0, st>>>(c, fa);
+        finalize<<<dim3(tiles(c.Z), c.nb, F), dim3(kBlock), 0, st>>>(c, fa);
     }
 };
 

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void engine_init_psi(CodeDev c, const float
 __global__ __launch_bounds__(64) void engine_frame_exit(FinArgs A) { frame_exit_work(A, blockIdx.x); }
 
 __global__ __launch_bounds__(kBlock) void engine_finalize(CodeDev c, FinArgs A) {
-    finalize_work(c, A, blockIdx.y, blockIdx.x);
+    finalize_work(c, A, blockIdx.z, blockIdx.y, blockIdx.x);
 }
 
 inline unsigned tiles_of(int n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -446,13 +446,13 @@ bool Engine::admit_one(const Request &rq, int s) {
     const int nfail = (rq.T + 1) * rq.F;
     engine_init_fail<<<dim3((nfail + kBlock - 1) / kBlock), dim3(kBlock), 0, stream>>>(
         D.fail, rq.F, rq.T, D.early_stop, D.check_from);
-    engine_pack_syndrome<<<dim3(tiles_of(c.Z), c.mb, rq.F), dim3(kBlock), 0, stream>>>(
+    engine_pack_syndrome<<<dim3(setup_tiles(c.Z), c.mb, rq.F), dim3(kBlock), 0, stream>>>(
         c, rq.syndrome, D.synbits, D.L.synbits_frame);
     if (c.NC > 0)
-        engine_init_totals<<<dim3(tiles_of(c.Z), c.NC, rq.F), dim3(kBlock), 0, stream>>>(
+        engine_init_totals<<<dim3(setup_tiles(c.Z), c.NC, rq.F), dim3(kBlock), 0, stream>>>(
             c, rq.llr, D.tot, D.L.tot_frame);
     if (c.ND1 > 0)
-        engine_init_psi<<<dim3(tiles_of(c.Z), c.ND1, rq.F), dim3(kBlock), 0, stream>>>(
+        engine_init_psi<<<dim3(setup_tiles(c.Z), c.ND1, rq.F), dim3(kBlock), 0, stream>>>(
             c, rq.llr, D.psi, D.L.psi_frame);
     table_dirty = true;
     return true;
@@ -478,7 +478,7 @@ void Engine::retire(int s) {
     fa.F = D.F;
     fa.T = D.T;
     engine_frame_exit<<<dim3(D.F), dim3(64), 0, stream>>>(fa);
-    engine_finalize<<<dim3(tiles_of(D.c.n), D.F), dim3(kBlock), 0, stream>>>(D.c, fa);
+    engine_finalize<<<dim3(tiles_of(D.c.Z), D.c.nb, D.F), dim3(kBlock), 0, stream>>>(D.c, fa);
     hipEvent_t ev = nullptr;
     if (!spare_events.empty()) {
         ev = spare_events.back();

@@ -1163,30 +1163,58 @@ __device__ __forceinline__ void variable_work(const CodeDev &c, const VnArgs &A,
     }
 }
 
+// The set-up steps below take kSetupPerThread positions per thread (256
+// apart), all loads issued before the first use; a row or column of Z
+// positions takes setup_tiles(Z) workgroups.
+constexpr int kSetupPerThread = 4;
+inline unsigned setup_tiles(int Z) {
+    return (unsigned)((Z + kBlock * kSetupPerThread - 1) / (kBlock * kSetupPerThread));
+}
+
 // Pack the syndrome bytes into 64-bit words per base row: bit a%64 of word a/64,
 // for check a of the relabelled row.
 __device__ __forceinline__ void pack_syndrome_work(const CodeDev &c, const uint8_t *syn,
                                                    uint64_t *synbits, size_t syn_frame, int f, int r,
                                                    unsigned tile) {
-    const int a = tile * kBlock + threadIdx.x;
-    const bool valid = a < c.Z;
-    int j = a - c.row_rot[r];  // the check's index in the code as given
-    j += (j < 0) ? c.Z : 0;
-    const int v = valid ? (syn[(size_t)f * c.m + (size_t)r * c.Z + j] & 1) : 0;
-    const unsigned long long bits = wave_ballot(v != 0);
-    if ((threadIdx.x & 63) == 0 && valid)
-        synbits[(size_t)f * syn_frame + (size_t)r * c.W + (a >> 6)] = bits;
+    const int Z = c.Z;
+    const int rot = c.row_rot[r];
+    const uint8_t *row = syn + (size_t)f * c.m + (size_t)r * Z;
+    int v[kSetupPerThread];
+#pragma unroll
+    for (int q = 0; q < kSetupPerThread; ++q) {
+        const int a = (int)((tile * kSetupPerThread + q) * kBlock + threadIdx.x);
+        int j = a - rot;  // the check's index in the code as given
+        j += (j < 0) ? Z : 0;
+        v[q] = a < Z ? (row[j] & 1) : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kSetupPerThread; ++q) {
+        const int a = (int)((tile * kSetupPerThread + q) * kBlock + threadIdx.x);
+        const unsigned long long bits = wave_ballot(v[q] != 0);
+        if ((threadIdx.x & 63) == 0 && a < Z)
+            synbits[(size_t)f * syn_frame + (size_t)r * c.W + (a >> 6)] = bits;
+    }
 }
 
 // Core totals of iteration 0: L_v = Q_v, in base 2 (both copies of the row).
 __device__ __forceinline__ void init_totals_work(const CodeDev &c, const float *llr, float *tot,
                                                  size_t tot_frame, int f, int k, unsigned tile) {
-    const int j = tile * kBlock + threadIdx.x;
-    if (j >= c.Z) return;
-    const float q = llr[(size_t)f * c.n + (size_t)c.core_col[k] * c.Z + j] * kLog2e;
+    const float *src = llr + (size_t)f * c.n + (size_t)c.core_col[k] * c.Z;
     float *row = tot + (size_t)f * tot_frame + (size_t)k * c.Zt;
-    row[j] = q;
-    row[j + c.Z] = q;
+    float q[kSetupPerThread];
+#pragma unroll
+    for (int u = 0; u < kSetupPerThread; ++u) {
+        const int j = (int)((tile * kSetupPerThread + u) * kBlock + threadIdx.x);
+        q[u] = j < c.Z ? src[j] * kLog2e : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kSetupPerThread; ++u) {
+        const int j = (int)((tile * kSetupPerThread + u) * kBlock + threadIdx.x);
+        if (j < c.Z) {
+            row[j] = q[u];
+            row[j + c.Z] = q[u];
+        }
+    }
 }
 
 // Degree-1 inputs in check order: Psi[a] = d1_input(Q_p), p the variable of
@@ -1195,12 +1223,24 @@ __device__ __forceinline__ void init_totals_work(const CodeDev &c, const float *
 __device__ __forceinline__ void init_psi_work(const CodeDev &c, const float *llr, float *psi,
                                               size_t psi_frame, int f, int k, unsigned tile) {
     const unsigned Z = (unsigned)c.Z;
-    const unsigned a = tile * kBlock + threadIdx.x;
-    if (a >= Z) return;
-    unsigned j = a + (unsigned)c.d1_shift[k];
-    j -= (j >= Z) ? Z : 0u;
-    const float q = llr[(size_t)f * c.n + (size_t)c.d1_col[k] * Z + j];
-    psi[(size_t)f * psi_frame + (size_t)k * c.Zp + a] = d1_input(q, c.d1_tdom[k] != 0, phi_consts());
+    const unsigned s = (unsigned)c.d1_shift[k];
+    const bool tdom = c.d1_tdom[k] != 0;
+    const float *src = llr + (size_t)f * c.n + (size_t)c.d1_col[k] * Z;
+    float *dst = psi + (size_t)f * psi_frame + (size_t)k * c.Zp;
+    const PhiConsts PK = phi_consts();
+    float q[kSetupPerThread];
+#pragma unroll
+    for (int u = 0; u < kSetupPerThread; ++u) {
+        const unsigned a = (tile * kSetupPerThread + u) * kBlock + threadIdx.x;
+        unsigned j = a + s;
+        j -= (j >= Z) ? Z : 0u;
+        q[u] = a < Z ? src[j] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kSetupPerThread; ++u) {
+        const unsigned a = (tile * kSetupPerThread + u) * kBlock + threadIdx.x;
+        if (a < Z) dst[a] = d1_input(q[u], tdom, PK);
+    }
 }
 
 struct FinArgs {
@@ -1240,32 +1280,35 @@ __device__ __forceinline__ void frame_exit_work(const FinArgs &A, int f) {
 }
 
 // Read-out of frame f (after frame_exit_work): hard decisions and posteriors at
-// the exit iteration.
-__device__ __forceinline__ void finalize_work(const CodeDev &c, const FinArgs &A, int f,
+// the exit iteration, for positions tile 256 + thread of base column col.  The
+// channel LLR is read only where it decides: degree-0 columns, degree-1
+// columns at t = 0, and posteriors at t = 0.
+__device__ __forceinline__ void finalize_work(const CodeDev &c, const FinArgs &A, int f, int col,
                                               unsigned tile) {
-    const int it = A.iters_out[f];
-    const int v = tile * kBlock + threadIdx.x;
-    if (v >= c.n) return;
     const int Z = c.Z;
-    const int col = v / Z;
-    const int j = v - col * Z;
-    const int kind = c.col_kind[col], ref = c.col_ref[col];
-    const float q = A.llr[(size_t)f * c.n + v];
-    float L = q;
-    int bit = q < 0.0f;
+    const int j = (int)(tile * kBlock + threadIdx.x);
+    if (j >= Z) return;
+    const int it = uniform_i32(A.iters_out + f);
+    const int kind = uniform_i32(c.col_kind + col), ref = uniform_i32(c.col_ref + col);
+    const size_t v = (size_t)f * c.n + (size_t)col * Z + j;
+    int bit;
+    float L = 0.0f;
     if (kind == COL_CORE) {
         const float Lb = A.tot[(size_t)f * A.tot_frame + (size_t)ref * c.Zt + j];
-        bit = Lb < 0.0f;
-        if (it > 0) L = Lb * kLn2;  // at t = 0 the posterior is Q itself
+        bit = Lb < 0.0f;  // at t = 0 the totals are Q log2(e): the sign of Q
+        if (A.llr_out) L = it > 0 ? Lb * kLn2 : A.llr[v];  // at t = 0 the posterior is Q itself
     } else if (kind == COL_DEG1 && it > 0) {
         int a = j - c.d1_shift[ref];
         a += (a < 0) ? Z : 0;
         const uint64_t wd = A.d1bits[it & 1][(size_t)f * A.d1_frame + (size_t)ref * c.W + (a >> 6)];
         bit = (int)((wd >> (a & 63)) & 1ull);
         if (A.llr_out) L = A.d1post[it & 1][(size_t)f * A.psi_frame + (size_t)ref * c.Zp + a];
+    } else {
+        L = A.llr[v];
+        bit = L < 0.0f;
     }
-    A.bits_out[(size_t)f * c.n + v] = (uint8_t)bit;
-    if (A.llr_out) A.llr_out[(size_t)f * c.n + v] = L;
+    A.bits_out[v] = (uint8_t)bit;
+    if (A.llr_out) A.llr_out[v] = L;
 }
 
 
