@@ -593,7 +593,7 @@ def main():
                          "engine batch; frontend: 8-D reconciliation + FP16 decode; serving: "
                          "Poisson requests through the engine")
     ap.add_argument("--duration", type=float, default=60.0, help="serving run length (s)")
-    ap.add_argument("--serve-caps", default="16e6,0",
+    ap.add_argument("--serve-caps", default="24e6,0",
                     help="serving: engine step caps in edge visits (first = reported; 0 = none)")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="serving: skip the one-request-at-a-time baseline")

@@ -143,12 +143,18 @@ def run_engine(ldpc, torch, pools, trace, budget_bytes, max_slots=64, msg_fp16=F
 
 def run_one_at_a_time(ldpc, torch, pools, trace, keep_outputs=False):
     """The same trace through plain FP32 ldpc_decode_batch, one request at a time."""
+    import sys
     outputs = {}
     t0 = time.perf_counter()
-    for r in trace:
+    last = t0
+    for i, r in enumerate(trace):
         now = time.perf_counter() - t0
         if r.arrival > now:
             time.sleep(r.arrival - now)
+        if time.perf_counter() - last > 20.0:  # progress, so a long replay is seen to run
+            last = time.perf_counter()
+            print(f"[serve] one at a time: {i} of {len(trace)} requests", file=sys.stderr,
+                  flush=True)
         code, q, s = _inputs(pools, r)
         bits, it, conv, _ = code.decode(q, s, r.max_iters)
         torch.cuda.current_stream().synchronize()
