@@ -66,9 +66,11 @@ __global__ __launch_bounds__(kBlock) void check_pass(CodeDev c, CnArgs A, FastDi
     check_pass_body<Msg, false, MODE, CPT>(c, A, tiles, rows, frames);
 }
 
-// The check pass of a code with owner groups: per frame, the (group, tile)
-// items of the t-domain rows come first, then the (row, tile) items of the
-// other common rows (row-list positions outside the t-domain class's range).
+// The check pass of a code with owner groups: per frame, the (row, tile)
+// items of the common rows outside the t-domain class (row-list positions
+// before and after its range) come first, then the (group, tile) items of the
+// t-domain rows.  The former carry several times the work per check of the
+// latter, so starting them first keeps them off the launch's tail.
 template <typename Msg, int MODE, int CPT>
 __global__ __launch_bounds__(kBlock) void check_pass_grouped(CodeDev c, CnArgs A, FastDiv per_frame,
                                                              FastDiv gtiles, FastDiv rtiles,
@@ -78,7 +80,10 @@ __global__ __launch_bounds__(kBlock) void check_pass_grouped(CodeDev c, CnArgs A
     const unsigned i = xcd_item(blockIdx.x, n);
     if (i >= n) return;
     const unsigned f = fdiv(i, per_frame);
-    const unsigned r = i - f * per_frame.d;
+    const unsigned r0 = i - f * per_frame.d;
+    const unsigned row_items = per_frame.d - group_items;
+    // r: the item's position with the group items first, as decoded below
+    const unsigned r = r0 < row_items ? r0 + group_items : r0 - row_items;
     if (r < group_items) {
         const unsigned g = fdiv(r, gtiles);
         group_work<MODE, Msg>(c, A, (int)f, (int)g, r - g * gtiles.d);

@@ -47,8 +47,8 @@ struct SlotHead {
     int32_t tiles;       // work tiles per row (check pass) or per core column (variable pass)
     int32_t rows;        // check pass: rows with their own items; variable pass: NC
     int32_t start_step, T, F, stride;  // stride: core_tab_stride (variable pass)
-    // check pass, per frame: gitems owner-group items (gtiles per group) first,
-    // then rows x tiles row items; in the vote-only step gitems = 0 and every
+    // check pass, per frame: rows x tiles row items, then gitems owner-group
+    // items (gtiles per group); in the vote-only step gitems = 0 and every
     // row has row items
     int32_t gitems, gtiles;
 };
@@ -85,7 +85,11 @@ __global__ __launch_bounds__(kBlock) void engine_check_pass(const SlotDesc *slot
     const int local = item - ix.begin[s];
     const int per_frame = H.gitems + H.rows * H.tiles;
     const int f = local / per_frame;
-    const int r = local - f * per_frame;
+    const int r0 = local - f * per_frame;
+    // the row items run first (they carry the most work per check), then the
+    // owner-group items; r is the position with the group items first
+    const int row_items = per_frame - H.gitems;
+    const int r = r0 < row_items ? r0 + H.gitems : r0 - row_items;
     const bool vote_only = t == H.T + 1;
     const SlotDesc &S = slots[s];
     CnArgs A{};
