@@ -120,6 +120,14 @@ typedef struct {
     int32_t n_timing_events; /* >= 4*max_iters when timing_events is set          */
     int32_t schedule;        /* LDPC_SCHEDULE_*: how the iterations are launched;
                                 results are identical on every schedule           */
+    int32_t streams;         /* per-iteration launches only (LDPC_SCHEDULE_LAUNCHES):
+                                0 = library choice: F >= 2 frames run as two halves
+                                on two streams when one iteration visits at least
+                                F * (stored + degree-1 blocks) * Z = 24,000,000
+                                edges (16,000,000 with msg_fp16), else one stream;
+                                1 = one stream; 2 = two halves whenever F >= 2.
+                                Ignored with timing_events (one stream).  Results
+                                are identical either way                          */
 } ldpc_decode_opts;
 
 /*
@@ -154,7 +162,7 @@ enum {
 
 /* Fill opts with the defaults {early_stop=1, check_from_iter=0, msg_fp16=0,
  * checks_per_thread=0, llr_out=NULL, timing_events=NULL, n_timing_events=0,
- * schedule=LDPC_SCHEDULE_AUTO}. */
+ * schedule=LDPC_SCHEDULE_AUTO, streams=0}. */
 void ldpc_decode_opts_init(ldpc_decode_opts *opts);
 
 /* The schedule (LDPC_SCHEDULE_LAUNCHES, _RESIDENT or _SPLIT) that
@@ -186,14 +194,18 @@ size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
  *   stream     hipStream_t or NULL
  * Messages are clamped through the Phi argument range [1e-7, 30].  Frames are
  * independent: frame f's outputs depend only on frame f's inputs, bit for bit,
- * whatever F and the other frames are.  On the per-iteration launches, F >= 2
- * frames without timing_events run as two halves, the second on a stream the
- * code handle owns, forked from and joined back into `stream` by events: the
- * decode stays ordered on `stream` like any other work there (and can be
- * captured into a graph from it); calls with one code handle from several host
- * threads are safe, and their second halves share that stream.
+ * whatever F and the other frames are.  On the per-iteration launches, a
+ * decode that opts.streams sends to two streams (by default F >= 2 frames with
+ * enough edge visits per iteration, and no timing_events) runs as two halves,
+ * the second on a stream the code handle owns, forked from and joined back into
+ * `stream` by events: the decode stays ordered on `stream` like any other work
+ * there (and can be captured into a graph from it); calls with one code handle
+ * from several host threads are safe, and their second halves share that
+ * stream.  Two streams double the launches per iteration, so they pay only
+ * where each half's iteration outlasts the host's launch rate.
  * Errors: LDPC_EINVAL (F < 1, max_iters < 0, check_from_iter < 0, null
- * pointer, checks_per_thread not 0/1/2/4, schedule out of range, too few
+ * pointer, checks_per_thread not 0/1/2/4, schedule out of range, streams not
+ * 0/1/2, too few
  * timing events), LDPC_EUNSUPPORTED (RESIDENT requested where it is not
  * possible), LDPC_EWORKSPACE, LDPC_EDEVICE (current device is not the code's
  * device, or a launch failed).

@@ -113,6 +113,7 @@ void ldpc_decode_opts_init(ldpc_decode_opts *o) {
     o->timing_events = nullptr;
     o->n_timing_events = 0;
     o->schedule = LDPC_SCHEDULE_AUTO;
+    o->streams = 0;
 }
 
 int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldpc_code **out) {
@@ -654,6 +655,24 @@ int ldpc_decode_schedule(const ldpc_code *code, int32_t F, const ldpc_decode_opt
 
 namespace {
 
+// Edge visits per iteration, F x (stored + degree-1 blocks) x Z, from which the
+// per-iteration launches run the frames as two halves on two streams by
+// default.  Two streams double the launches of an iteration (4 instead of 2,
+// about 17 us of host submission against 7 us), so they pay only where each
+// half's iteration outlasts that.  Measured on the rate-0.02 template at
+// Z = 2048 to 6667 and 2 to 16 frames, 100 iterations without convergence: one
+// stream faster up to 22M visits with float32 messages and 15M with half, two
+// faster from 24M and 16M (up to 7% and 10% at 30M-48M).
+constexpr int64_t kTwoStreamEdgesF32 = 24000000;
+constexpr int64_t kTwoStreamEdgesF16 = 16000000;
+
+bool two_streams(const ldpc_code *code, int F, const ldpc_decode_opts &o) {
+    if (F < 2 || o.timing_events || o.streams == 1) return false;
+    if (o.streams == 2) return true;
+    const int64_t edges = (int64_t)F * (code->dev.NS + code->dev.ND1) * code->dev.Z;
+    return edges >= (o.msg_fp16 ? kTwoStreamEdgesF16 : kTwoStreamEdgesF32);
+}
+
 // The body of both decode entry points.  noalloc: `workspace` is ignored and
 // the decode runs in the device's fixed scratch region.
 int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const uint8_t *syndrome,
@@ -673,6 +692,8 @@ int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const 
         return fail_with(LDPC_EINVAL, "checks_per_thread = %d is not 0, 1, 2 or 4",
                          o.checks_per_thread);
     if (o.check_from_iter < 0) return fail_with(LDPC_EINVAL, "check_from_iter < 0");
+    if (o.streams < 0 || o.streams > 2)
+        return fail_with(LDPC_EINVAL, "streams = %d is not 0, 1 or 2", o.streams);
     if (o.timing_events && (int64_t)o.n_timing_events < 4ll * max_iters)
         return fail_with(LDPC_EINVAL, "%d timing events; need 4*max_iters = %lld",
                          o.n_timing_events, 4ll * max_iters);
@@ -730,12 +751,14 @@ int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const 
         e = ldpc::enqueue_resident(l, WL, code->lds_limit);
     } else if (sched == LDPC_SCHEDULE_SPLIT) {
         e = ldpc::enqueue_split(l, WL);
-    } else {
+    } else if (two_streams(code, F, o)) {
         ldpc_code *mc = const_cast<ldpc_code *>(code);
         std::lock_guard<std::mutex> g(mc->aux_lock);
         l.aux = mc->aux;
         l.fork = mc->fork;
         l.join = mc->join;
+        e = ldpc::enqueue_decode(l);
+    } else {
         e = ldpc::enqueue_decode(l);
     }
     if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));

@@ -60,7 +60,7 @@ class DecodeOpts(ctypes.Structure):
         ("msg_fp16", ctypes.c_int32), ("checks_per_thread", ctypes.c_int32),
         ("llr_out", ctypes.c_void_p),
         ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
-        ("schedule", ctypes.c_int32),
+        ("schedule", ctypes.c_int32), ("streams", ctypes.c_int32),
     ]
 
 
@@ -150,10 +150,12 @@ def _stream_handle(stream):
 
 
 def make_opts(early_stop=True, check_from_iter=0, msg_fp16=False, llr_out_ptr=None,
-              timing_events=None, checks_per_thread=0, schedule="auto") -> DecodeOpts:
+              timing_events=None, checks_per_thread=0, schedule="auto",
+              streams=0) -> DecodeOpts:
     o = DecodeOpts()
     load().ldpc_decode_opts_init(ctypes.byref(o))
     o.checks_per_thread = int(checks_per_thread)
+    o.streams = int(streams)
     o.schedule = _SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.early_stop = int(bool(early_stop))
     o.check_from_iter = int(check_from_iter)
@@ -227,11 +229,13 @@ class Code:
 
     def decode(self, llr, syndrome, max_iters: int, early_stop=True, check_from_iter=0,
                msg_fp16=False, want_llr=False, workspace=None, out=None, stream=None,
-               timing_events=None, checks_per_thread=0, schedule="auto"):
+               timing_events=None, checks_per_thread=0, schedule="auto", streams=0):
         """Decode frames llr [F][n] float32 / syndrome [F][m] uint8 (CUDA tensors).
 
         Returns (bits uint8 [F][n], iters int32 [F], converged uint8 [F], L or None),
         all CUDA tensors, valid once ``stream`` (default: current) is synchronised.
+        ``streams``: 0 library choice, 1 one stream, 2 two halves of the frames on
+        two streams (per-iteration launches; as ldpc_decode_opts.streams).
         """
         import torch
         if llr.dtype != torch.float32 or syndrome.dtype != torch.uint8:
@@ -255,7 +259,7 @@ class Code:
             workspace = self.alloc_workspace(F, max_iters, msg_fp16, want_llr, dev)
         opts = make_opts(early_stop, check_from_iter, msg_fp16,
                          L.data_ptr() if L is not None else None, timing_events,
-                         checks_per_thread, schedule)
+                         checks_per_thread, schedule, streams)
         st = load().ldpc_decode_batch(
             self._h, F, llr.data_ptr(), syndrome.data_ptr(), int(max_iters),
             bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ctypes.byref(opts),
@@ -265,7 +269,7 @@ class Code:
 
     def decode_noalloc(self, llr, syndrome, max_iters: int, early_stop=True, check_from_iter=0,
                        msg_fp16=False, out=None, stream=None, checks_per_thread=0,
-                       schedule="auto"):
+                       schedule="auto", streams=0):
         """ldpc_decode_batch_noalloc: as ``decode`` (no posteriors), with the decode
         state in the library's fixed per-device scratch region instead of a
         workspace.  ``out`` = (bits, iters, converged) preallocated tensors, else
@@ -286,7 +290,7 @@ class Code:
                    torch.empty(F, dtype=torch.uint8, device=llr.device))
         bits, iters, conv = out[:3]
         opts = make_opts(early_stop, check_from_iter, msg_fp16, None, None, checks_per_thread,
-                         schedule)
+                         schedule, streams)
         st = load().ldpc_decode_batch_noalloc(
             self._h, F, llr.data_ptr(), syndrome.data_ptr(), int(max_iters), bits.data_ptr(),
             iters.data_ptr(), conv.data_ptr(), ctypes.byref(opts), _stream_handle(stream))

@@ -289,6 +289,10 @@ def test_invalid_arguments(ldpc):
     assert call(2, 10, ws.data_ptr(), ws.numel()) == ldpc.LDPC_OK
     torch.cuda.synchronize()
     assert np.all(it.cpu().numpy() <= 10)
+    for bad in (-1, 3):
+        with pytest.raises(ldpc.LdpcError) as err:
+            g.decode(Q, s, 10, streams=bad)
+        assert err.value.status == ldpc.LDPC_EINVAL
     with pytest.raises(ldpc.LdpcError):
         ldpc.Code(np.array([[0, Z]], dtype=np.int32), Z)
     with pytest.raises(ldpc.LdpcError):
@@ -351,9 +355,10 @@ def test_timing_events(ldpc, oracle_mod):
 
 @pytest.mark.parametrize("Z,F", [(64, 5), (1000, 3)])
 def test_two_streams_match_one(ldpc, oracle_mod, Z, F):
-    """Without per-pass events the launches run the frames in two halves on
-    two streams (here 3 + 2 and 2 + 1 frames); with events they run on one.
-    Bits, iteration counts, flags and posteriors agree exactly, FP32 and FP16."""
+    """streams=2 runs the frames in two halves on two streams (here 3 + 2 and
+    2 + 1 frames); streams=1, and any call with per-pass events, runs them on
+    one.  Bits, iteration counts, flags and posteriors agree exactly, FP32 and
+    FP16."""
     base = synth.template_base(144, Z, seed=1)
     g = ldpc.Code(base, Z)
     x, Q = synth.biawgn_frames(g.n, F, -13.5, seed=50 + F)
@@ -361,13 +366,17 @@ def test_two_streams_match_one(ldpc, oracle_mod, Z, F):
     T = 30
     _say("two streams vs one", Z, F)
     for fp16 in (False, True):
-        two = _gpu_decode(g, Q, s, T, msg_fp16=fp16, want_llr=True, schedule="launches")
-        ev = _HipEvents(4 * T)
+        two = _gpu_decode(g, Q, s, T, msg_fp16=fp16, want_llr=True, schedule="launches",
+                          streams=2)
         one = _gpu_decode(g, Q, s, T, msg_fp16=fp16, want_llr=True, schedule="launches",
-                          timing_events=ev.arr)
+                          streams=1)
+        ev = _HipEvents(4 * T)
+        timed = _gpu_decode(g, Q, s, T, msg_fp16=fp16, want_llr=True, schedule="launches",
+                            timing_events=ev.arr, streams=2)
         ev.close()
-        for name, a, b in zip(("bits", "iters", "converged", "llr"), two, one):
+        for name, a, b, c in zip(("bits", "iters", "converged", "llr"), two, one, timed):
             assert np.array_equal(a, b), (name, fp16)
+            assert np.array_equal(a, c), (name, fp16)
 
 
 @pytest.mark.parametrize("schedule", ["launches", "resident"])
