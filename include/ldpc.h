@@ -64,7 +64,7 @@ typedef struct {
     int64_t owned_edges;    /* edges of owner blocks: per row with two core blocks
                                and one degree-1 block, the core block whose
                                messages the check pass sums per owner group      */
-    int32_t owner_groups;   /* owner groups (up to 24 such rows sharing an owner
+    int32_t owner_groups;   /* owner groups (up to 12 such rows sharing an owner
                                core column); the variable pass reads one partial
                                sum per group instead of the group's messages     */
 } ldpc_code_info_t;

@@ -6,13 +6,20 @@ Tunables:
   circulant block.  More checks per thread amortise the row's table reads and
   keep more loads in flight per thread; fewer give more workgroups for small Z
   and few frames;
-- for a single decode call, also the schedule: per-iteration launches or the
-  frame-resident kernel (one workgroup per frame, state in LDS), where the
+- for a single decode call, also the number of streams of the per-iteration
+  launches (one, or the two halves of the frames on two streams: two double
+  the launches of an iteration and pay only where each half's iteration
+  outlasts the host's launch rate), and the schedule: per-iteration launches,
+  the frame-resident kernel (one workgroup per frame, state in LDS) or the
+  frame-split kernel (a few co-resident workgroups per frame), where the
   code's state fits.
 
 Results do not depend on the choice (the arithmetic is identical), so the tuner
-only measures time: each candidate decodes the actual batch for a few
-iterations with early stop off, timed with HIP events, and the fastest wins.
+only measures time: each candidate decodes the actual batch with early stop
+off, timed with HIP events, and the fastest wins.  A single decode is timed at
+its own iteration count, so that per-call costs (set-up, read-out, the fork and
+join of two streams) weigh as they will in use: at 8 iterations one stream
+looked faster on the n = 1,000,050 batch of 8 frames, at 100 two streams are.
 Choices are cached in a JSON file keyed by the workload's shape, precision and
 device name (LDPC_AUTOTUNE_CACHE overrides the path).
 """
@@ -77,27 +84,41 @@ def _time(fn, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
-def tune_decode(code, llr, syndrome, msg_fp16=False, iters=8, use_cache=True):
+def name_of(cfg) -> str:
+    """The candidate name of a tune_decode configuration."""
+    if cfg["schedule"] == "launches":
+        return f"launches/{cfg['checks_per_thread']}/{cfg['streams']}"
+    return cfg["schedule"]
+
+
+def tune_decode(code, llr, syndrome, msg_fp16=False, iters=100, use_cache=True):
     """Best decode configuration for ldpc_decode_batch on this batch.
 
-    Returns (best, ms): best = {"schedule": "launches" | "resident",
-    "checks_per_thread": 1 | 2 | 4 (0 for the resident schedule)}, ms = the time
-    of each candidate, keyed "launches/<cpt>" or "resident".
+    Returns (best, ms): best = keyword arguments of Code.decode,
+    {"schedule": "launches", "checks_per_thread": 1 | 2 | 4, "streams": 1 | 2}
+    or {"schedule": "resident" | "split", "checks_per_thread": 0, "streams": 0};
+    ms = the time of each candidate, keyed by name_of: "launches/<cpt>/<streams>",
+    "resident" or "split".  iters: the decode's max_iters (part of the cache key).
     """
     from paper_1702_07740_amd import ldpc
-    key = _key("decode2", [_shape(code, llr.shape[0])], msg_fp16)
+    F = llr.shape[0]
+    key = _key("decode3", [_shape(code, F), int(iters)], msg_fp16)
     if use_cache:
         hit = _load_cache().get(key)
         if hit:
             return hit["best"], hit["ms"]
-    ws = code.alloc_workspace(llr.shape[0], iters, msg_fp16=msg_fp16)
-    cands = {f"launches/{cpt}": {"schedule": "launches", "checks_per_thread": cpt}
-             for cpt in CANDIDATES}
-    try:
-        code.schedule(F=llr.shape[0], msg_fp16=msg_fp16, schedule="resident")
-        cands["resident"] = {"schedule": "resident", "checks_per_thread": 0}
-    except ldpc.LdpcError:
-        pass  # the frame's state does not fit one workgroup's LDS
+    ws = code.alloc_workspace(F, iters, msg_fp16=msg_fp16)
+    cands = {}
+    for cpt in CANDIDATES:
+        for streams in ((1, 2) if F >= 2 else (1,)):
+            cfg = {"schedule": "launches", "checks_per_thread": cpt, "streams": streams}
+            cands[name_of(cfg)] = cfg
+    for sch in ("resident", "split"):
+        try:
+            code.schedule(F=F, msg_fp16=msg_fp16, schedule=sch)
+            cands[sch] = {"schedule": sch, "checks_per_thread": 0, "streams": 0}
+        except ldpc.LdpcError:
+            pass  # the frame's state does not fit one workgroup's LDS, or too many frames
     ms = {}
     for name, cfg in cands.items():
         ms[name] = _time(lambda: code.decode(llr, syndrome, iters, early_stop=False,

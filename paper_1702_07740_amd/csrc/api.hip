@@ -577,22 +577,26 @@ namespace {
 // iteration, fitted to measurements on MI355X: the resident schedule takes
 // about kResidentUnitNs per (base row, 64 checks) unit of a frame, for every
 // round of up to kResidentFramesPerRound frames (one workgroup per CU); the
-// launches take kLaunchFixedNs plus kLaunchWgNs per workgroup of the two
-// passes (256-thread check tiles of 256 * cpt checks, variable tiles of 128
-// or, with half messages, 256 variables).
+// launches (one stream) take kLaunchFixedNs plus kLaunchWgNs per workgroup of
+// the two passes: check items of one owner group over 256 positions or of one
+// other row over 256 * cpt checks, variable items of 512 variables.  On the
+// rate-0.02 template at Z = 64 (15 check and 6 variable items per frame) the
+// launches measured 10.1, 13.8, 27.3 and 75 us per iteration at 16, 64, 256
+// and 1024 frames, the resident schedule 11.4-11.6 us per round.
 constexpr double kResidentUnitNs = 80.0;
 constexpr int kResidentFramesPerRound = 256;
-constexpr double kLaunchFixedNs = 7000.0;
-constexpr double kLaunchWgNs = 2.35;
+constexpr double kLaunchFixedNs = 8800.0;
+constexpr double kLaunchWgNs = 3.2;
 
-bool resident_pays(const CodeDev &c, int F, int cpt, bool fp16) {
+bool resident_pays(const CodeDev &c, int F, int cpt) {
     const double units = (double)c.mb * c.W;
     const double rounds = (double)((F + kResidentFramesPerRound - 1) / kResidentFramesPerRound);
     const double t_res = rounds * units * kResidentUnitNs;
-    const int vn = fp16 ? 256 : 128;
-    const double wgs = (double)F * ((double)c.mb * ((c.Z + 256 * cpt - 1) / (256 * cpt)) +
-                                    (double)c.NC * ((c.Z + vn - 1) / vn));
-    return t_res < kLaunchFixedNs + kLaunchWgNs * wgs;
+    const int gt = (c.Z + 255) / 256, rt = (c.Z + 256 * cpt - 1) / (256 * cpt);
+    const int grouped_rows = c.n_groups > 0 ? c.n_tdom : 0;
+    const double check = (double)c.n_groups * gt + (double)(c.mb - grouped_rows) * rt;
+    const double var = (double)c.NC * ((c.Z + 511) / 512);
+    return t_res < kLaunchFixedNs + kLaunchWgNs * (double)F * (check + var);
 }
 
 // Checks per thread when the caller leaves the choice to the library: 1 for
@@ -624,8 +628,7 @@ int resolve_schedule(const ldpc_code *code, int F, const ldpc_decode_opts &o, in
     if (o.schedule == LDPC_SCHEDULE_AUTO)
         *out = (possible && resident_pays(code->dev, F, o.checks_per_thread == 0
                                                             ? default_cpt(code->dev)
-                                                            : o.checks_per_thread,
-                                          o.msg_fp16 != 0))
+                                                            : o.checks_per_thread))
                    ? LDPC_SCHEDULE_RESIDENT
                    : LDPC_SCHEDULE_LAUNCHES;
     else

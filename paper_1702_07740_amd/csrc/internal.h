@@ -46,9 +46,12 @@ constexpr int kRowDescWords = 20;
 // sum per group, and the variable pass reads the partial instead of the
 // group's messages.
 // Measured on the rate-0.02 template (24 owned rows per core column) at
-// Z = 6667: groups of 24 rows beat 4, 6, 8, 12 and 16 (fewer partials for the
-// variable pass, and the owner total read once for more rows).
-constexpr int kGroupRows = 24;
+// Z = 6667, 8 frames decoded as two halves on two streams: groups of 12 rows
+// 2374 Mbit/s, against 2333 (16), 2231 (24) and 2245 (8); with half messages
+// 3130 against 2981, 2850 and 2727.  Twice as many group items as with 24
+// outweigh the extra partials the variable pass reads (with one stream per
+// decode, 24 had measured fastest).
+constexpr int kGroupRows = 12;
 constexpr int kGroupDescWords = 8;
 
 // Words of a row's descriptor for the frame-resident schedule (see

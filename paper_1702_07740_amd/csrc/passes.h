@@ -915,7 +915,7 @@ __device__ __forceinline__ void group_batch(const GroupView<Msg> &G, int k0, flo
 }
 
 // Rows of an owner group whose loads are in flight together (measured: 4
-// beats 2, 3, 6 and 8 at 24 rows per group).
+// beats 2, 3, 6 and 8 at 24 rows per group, and 3 and 6 at 12).
 constexpr int kGroupBatch = 4;
 
 template <int MODE, typename Msg, bool FULL>

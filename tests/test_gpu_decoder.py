@@ -612,7 +612,7 @@ def test_schedule_does_not_change_results(ldpc, oracle_mod, Z):
 def test_owner_groups_of_the_templates(ldpc, oracle_mod, rate, Z):
     """Every type-2 row (two core blocks, one degree-1 block) owns one core
     block, the 6 core columns own equally many rows, and each column's owned
-    rows form groups of at most 24; codes without such rows have none.  The
+    rows form groups of at most 12; codes without such rows have none.  The
     relabelling these groups rest on leaves the syndrome of a word unchanged:
     the library's H x equals the oracle's for random words."""
     base = synth.template_for_rate(rate, Z, seed=1)
@@ -620,7 +620,7 @@ def test_owner_groups_of_the_templates(ldpc, oracle_mod, rate, Z):
     n_type2 = synth.N_DEG1_FOR_RATE[rate]
     per_col = n_type2 // synth.N_CORE
     assert g.info["owned_edges"] == n_type2 * Z
-    assert g.info["owner_groups"] == synth.N_CORE * -(-per_col // 24)
+    assert g.info["owner_groups"] == synth.N_CORE * -(-per_col // 12)
     o = oracle_mod.OracleCode(base, Z)
     x = np.random.default_rng(7).integers(0, 2, size=(3, g.n), dtype=np.uint8)
     s = g.syndrome(torch.from_numpy(x).cuda()).cpu().numpy()

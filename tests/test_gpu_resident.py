@@ -217,8 +217,9 @@ def test_many_frames(ldpc, oracle_mod):
 
 
 def test_autotuner_picks_the_fastest_schedule(ldpc, oracle_mod, tmp_path, monkeypatch):
-    """The autotuner times every (schedule, checks per thread) candidate on the
-    actual batch and returns the fastest; its choice decodes identically."""
+    """The autotuner times every (schedule, checks per thread, streams)
+    candidate on the actual batch and returns the fastest; its choice decodes
+    identically."""
     from paper_1702_07740_amd import autotune
     monkeypatch.setenv("LDPC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     Z, F = 64, 128
@@ -229,9 +230,9 @@ def test_autotuner_picks_the_fastest_schedule(ldpc, oracle_mod, tmp_path, monkey
     dQ, ds = _dev(Q), _dev(s)
     _say("autotune schedule", Z, F)
     best, ms = autotune.tune_decode(g, dQ, ds)
-    assert set(ms) == {"launches/1", "launches/2", "launches/4", "resident"}
-    name = "resident" if best["schedule"] == "resident" else f"launches/{best['checks_per_thread']}"
-    assert ms[name] == min(ms.values())
+    assert set(ms) == {f"launches/{c}/{n}" for c in (1, 2, 4) for n in (1, 2)} | {"resident",
+                                                                                    "split"}
+    assert ms[autotune.name_of(best)] == min(ms.values())
     again, _ = autotune.tune_decode(g, dQ, ds)  # from the cache
     assert again == best
     ref = _run(g, Q, s, 50, schedule="launches")
