@@ -660,12 +660,18 @@ namespace {
 
 // Edge visits per iteration, F x (stored + degree-1 blocks) x Z, from which the
 // per-iteration launches run the frames as two halves on two streams by
-// default.  Two streams double the launches of an iteration (4 instead of 2,
-// about 17 us of host submission against 7 us), so they pay only where each
-// half's iteration outlasts that.  Measured on the rate-0.02 template at
-// Z = 2048 to 6667 and 2 to 16 frames, 100 iterations without convergence: one
-// stream faster up to 22M visits with float32 messages and 15M with half, two
-// faster from 24M and 16M (up to 7% and 10% at 30M-48M).
+// default.  Two streams double the launches of an iteration, so a decode whose
+// iterations are short runs into the launch rate: 100 iterations take at least
+// about 1.05 ms on two streams against 0.63 ms on one.  Measured on the
+// rate-0.02 and rate-0.05 templates at Z = 2048 to 6667 and 2 to 16 frames,
+// 100 iterations, one decode repeated: two streams faster from 14.7M visits
+// with float32 messages and from 12M with half, one stream faster or level
+// below (by up to 40% at 2M-6M).  A stream of different decodes submitted back
+// to back gains less: the host's launches overlap the previous decode's GPU
+// work only while the GPU is the bottleneck, and once frames converge it is
+// not.  Nine rate-0.02/0.05/0.1 decodes of 7-8 frames in sequence ran at 2094
+// Mbit/s with thresholds of 14M / 12M and at 2354 with 24M / 16M, and the
+// 8-frame n = 1,000,050 decode (24.0M) gained 8-11% from two streams.
 constexpr int64_t kTwoStreamEdgesF32 = 24000000;
 constexpr int64_t kTwoStreamEdgesF16 = 16000000;
 
