@@ -128,6 +128,20 @@ typedef struct {
                                 1 = one stream; 2 = two halves whenever F >= 2.
                                 Ignored with timing_events (one stream).  Results
                                 are identical either way                          */
+    int32_t graphs;          /* per-iteration launches on one stream, at most
+                                F * (stored + degree-1 blocks) * Z = 1,000,000
+                                edge visits per iteration (where the host's
+                                launches can bound a decode): 0 = library
+                                choice: a call that repeats an earlier call's F,
+                                max_iters, options and pointers is captured into
+                                a HIP graph at its second occurrence and
+                                replayed from the third (the code handle keeps 4
+                                such graphs, least recently used replaced); not
+                                with timing_events, not while `stream` is itself
+                                being captured, never in
+                                ldpc_decode_batch_noalloc; 1 = launch the
+                                kernels one by one every time.  Results are
+                                identical either way                             */
 } ldpc_decode_opts;
 
 /*
@@ -162,7 +176,7 @@ enum {
 
 /* Fill opts with the defaults {early_stop=1, check_from_iter=0, msg_fp16=0,
  * checks_per_thread=0, llr_out=NULL, timing_events=NULL, n_timing_events=0,
- * schedule=LDPC_SCHEDULE_AUTO, streams=0}. */
+ * schedule=LDPC_SCHEDULE_AUTO, streams=0, graphs=0}. */
 void ldpc_decode_opts_init(ldpc_decode_opts *opts);
 
 /* The schedule (LDPC_SCHEDULE_LAUNCHES, _RESIDENT or _SPLIT) that
@@ -205,7 +219,7 @@ size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t F, int32_t max_iters,
  * where each half's iteration outlasts the host's launch rate.
  * Errors: LDPC_EINVAL (F < 1, max_iters < 0, check_from_iter < 0, null
  * pointer, checks_per_thread not 0/1/2/4, schedule out of range, streams not
- * 0/1/2, too few
+ * 0/1/2, graphs not 0/1, too few
  * timing events), LDPC_EUNSUPPORTED (RESIDENT requested where it is not
  * possible), LDPC_EWORKSPACE, LDPC_EDEVICE (current device is not the code's
  * device, or a launch failed).

@@ -22,10 +22,28 @@ struct ldpc_code {
     CodeDev dev;            // sizes + device table pointers
     int32_t *table;         // one device allocation holding every table
     // the second stream of two-stream decodes, its fork and join events, and
-    // the lock that keeps one call's record / wait pairs together
+    // the lock that keeps one call's record / wait pairs together (it also
+    // guards the decode graphs below)
     hipStream_t aux = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     std::mutex aux_lock;
+    // Decode graphs.  A small one-stream decode on the per-iteration launches
+    // that repeats an earlier call's sizes, options and pointers is captured
+    // into a HIP graph (on `cap`, a stream of its own) at its second call and
+    // replayed from the third, which saves the host two launches per
+    // iteration.  kGraphSlots
+    // entries, the least recently used one replaced (its count starts again).
+    static constexpr int kGraphSlots = 4;
+    static constexpr int kGraphKeyWords = 16;
+    struct GraphSlot {
+        int64_t key[kGraphKeyWords] = {};
+        int seen = 0;                  // calls with this key; -1: capture failed
+        hipGraphExec_t exec = nullptr;
+        uint64_t used = 0;
+    };
+    hipStream_t cap = nullptr;
+    GraphSlot graphs[kGraphSlots];
+    uint64_t graph_clock = 0;
 };
 
 namespace {
@@ -114,6 +132,7 @@ void ldpc_decode_opts_init(ldpc_decode_opts *o) {
     o->n_timing_events = 0;
     o->schedule = LDPC_SCHEDULE_AUTO;
     o->streams = 0;
+    o->graphs = 0;
 }
 
 int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldpc_code **out) {
@@ -450,6 +469,10 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
         code->aux = nullptr;
         code->fork = code->join = nullptr;
     }
+    // the capture stream of the decode graphs (default priority); without it
+    // every decode launches its kernels one by one
+    if (hipStreamCreateWithFlags(&code->cap, hipStreamNonBlocking) != hipSuccess)
+        code->cap = nullptr;
     // set-up of the no-allocation decode on this device (its failure is
     // reported by ldpc_decode_batch_noalloc, which retries the lookup)
     (void)scratch_setup(code->device);
@@ -543,6 +566,9 @@ int ldpc_code_create(int32_t mb, int32_t nb, const int32_t *base, int32_t Z, ldp
 
 void ldpc_code_destroy(ldpc_code *code) {
     if (!code) return;
+    for (auto &g : code->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (code->cap) (void)hipStreamDestroy(code->cap);
     if (code->aux) (void)hipStreamSynchronize(code->aux);
     if (code->join) (void)hipEventDestroy(code->join);
     if (code->fork) (void)hipEventDestroy(code->fork);
@@ -682,6 +708,93 @@ bool two_streams(const ldpc_code *code, int F, const ldpc_decode_opts &o) {
     return edges >= (o.msg_fp16 ? kTwoStreamEdgesF16 : kTwoStreamEdgesF32);
 }
 
+// The words that identify a decode for the graph cache: everything a
+// captured launch sequence bakes in (sizes, options, pointers, stream mode).
+void graph_key(const ldpc::DecodeLaunch &l, bool two, int64_t (&k)[ldpc_code::kGraphKeyWords]) {
+    int i = 0;
+    k[i++] = l.F;
+    k[i++] = l.T;
+    k[i++] = l.early_stop;
+    k[i++] = l.check_from;
+    k[i++] = l.fp16;
+    k[i++] = l.cpt;
+    k[i++] = two ? 1 : 0;
+    k[i++] = (int64_t)(uintptr_t)l.llr;
+    k[i++] = (int64_t)(uintptr_t)l.syndrome;
+    k[i++] = (int64_t)(uintptr_t)l.bits_out;
+    k[i++] = (int64_t)(uintptr_t)l.iters_out;
+    k[i++] = (int64_t)(uintptr_t)l.conv_out;
+    k[i++] = (int64_t)(uintptr_t)l.llr_out;
+    k[i++] = (int64_t)(uintptr_t)l.ws;
+    while (i < ldpc_code::kGraphKeyWords) k[i++] = 0;
+}
+
+// Enqueue a decode on the per-iteration launches through the code's graph
+// cache (caller holds aux_lock): replay the cached graph of this exact call,
+// capture it at the key's second call, else launch the kernels directly.  A
+// failed capture falls back to direct launches for that key.
+hipError_t graph_decode(ldpc_code *mc, ldpc::DecodeLaunch l, bool two) {
+    int64_t key[ldpc_code::kGraphKeyWords];
+    graph_key(l, two, key);
+    ldpc_code::GraphSlot *s = nullptr;
+    for (auto &g : mc->graphs)
+        if (std::equal(key, key + ldpc_code::kGraphKeyWords, g.key)) s = &g;
+    if (!s) {
+        s = &mc->graphs[0];
+        for (auto &g : mc->graphs)
+            if (g.used < s->used) s = &g;
+        if (s->exec) (void)hipGraphExecDestroy(s->exec);
+        *s = ldpc_code::GraphSlot{};
+        std::copy(key, key + ldpc_code::kGraphKeyWords, s->key);
+    }
+    s->used = ++mc->graph_clock;
+    if (!s->exec) {
+        if (s->seen < 0 || ++s->seen < 2 || !mc->cap) return ldpc::enqueue_decode(l);
+        const hipStream_t caller = l.stream;
+        l.stream = mc->cap;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(mc->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t el = ldpc::enqueue_decode(l);
+            e = hipStreamEndCapture(mc->cap, &graph);
+            if (el != hipSuccess) e = el;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&s->exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        l.stream = caller;
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            s->exec = nullptr;
+            s->seen = -1;
+            return ldpc::enqueue_decode(l);
+        }
+    }
+    return hipGraphLaunch(s->exec, l.stream);
+}
+
+// Edge visits per iteration up to which a repeated decode is replayed from a
+// graph.  Graphs pay where the host's two launches per iteration take about
+// as long as the iteration itself: 16 frames of the n = 9,600 rate-0.02 code
+// (0.46M visits) went from 1.01 to 0.90 ms per decode.  A larger decode is
+// bound by the GPU, and replaying it gains nothing and costs a little: nine
+// different decodes of 1.3M-24M visits in sequence ran 3% slower (2194-2260
+// against 2317-2326 Mbit/s), and two-stream decodes lost their overlap in
+// part (8 frames of n = 1,000,050 with FP16 messages -1.7%, 32 frames -3%).
+constexpr int64_t kGraphMaxEdges = 1000000;
+
+bool graph_pays(const ldpc_code *code, int F, bool two) {
+    const int64_t edges = (int64_t)F * (code->dev.NS + code->dev.ND1) * code->dev.Z;
+    return !two && edges <= kGraphMaxEdges;
+}
+
+// Whether `stream` is being captured by its owner (then the kernels go into
+// that capture one by one).  A failed query counts as capturing.
+bool stream_capturing(hipStream_t stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) != hipSuccess) return true;
+    return st != hipStreamCaptureStatusNone;
+}
+
 // The body of both decode entry points.  noalloc: `workspace` is ignored and
 // the decode runs in the device's fixed scratch region.
 int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const uint8_t *syndrome,
@@ -703,6 +816,8 @@ int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const 
     if (o.check_from_iter < 0) return fail_with(LDPC_EINVAL, "check_from_iter < 0");
     if (o.streams < 0 || o.streams > 2)
         return fail_with(LDPC_EINVAL, "streams = %d is not 0, 1 or 2", o.streams);
+    if (o.graphs < 0 || o.graphs > 1)
+        return fail_with(LDPC_EINVAL, "graphs = %d is not 0 or 1", o.graphs);
     if (o.timing_events && (int64_t)o.n_timing_events < 4ll * max_iters)
         return fail_with(LDPC_EINVAL, "%d timing events; need 4*max_iters = %lld",
                          o.n_timing_events, 4ll * max_iters);
@@ -760,15 +875,18 @@ int decode_batch_impl(const ldpc_code *code, int32_t F, const float *llr, const 
         e = ldpc::enqueue_resident(l, WL, code->lds_limit);
     } else if (sched == LDPC_SCHEDULE_SPLIT) {
         e = ldpc::enqueue_split(l, WL);
-    } else if (two_streams(code, F, o)) {
-        ldpc_code *mc = const_cast<ldpc_code *>(code);
-        std::lock_guard<std::mutex> g(mc->aux_lock);
-        l.aux = mc->aux;
-        l.fork = mc->fork;
-        l.join = mc->join;
-        e = ldpc::enqueue_decode(l);
     } else {
-        e = ldpc::enqueue_decode(l);
+        ldpc_code *mc = const_cast<ldpc_code *>(code);
+        const bool two = two_streams(code, F, o);
+        const bool graph = !noalloc && o.graphs == 0 && !l.events && graph_pays(code, F, two) &&
+                           !stream_capturing(l.stream);
+        std::lock_guard<std::mutex> g(mc->aux_lock);
+        if (two) {
+            l.aux = mc->aux;
+            l.fork = mc->fork;
+            l.join = mc->join;
+        }
+        e = graph ? graph_decode(mc, l, two) : ldpc::enqueue_decode(l);
     }
     if (e != hipSuccess) return fail_with(LDPC_EDEVICE, "launch: %s", hipGetErrorString(e));
     return LDPC_OK;

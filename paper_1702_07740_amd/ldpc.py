@@ -60,7 +60,7 @@ class DecodeOpts(ctypes.Structure):
         ("msg_fp16", ctypes.c_int32), ("checks_per_thread", ctypes.c_int32),
         ("llr_out", ctypes.c_void_p),
         ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
-        ("schedule", ctypes.c_int32), ("streams", ctypes.c_int32),
+        ("schedule", ctypes.c_int32), ("streams", ctypes.c_int32), ("graphs", ctypes.c_int32),
     ]
 
 
@@ -151,11 +151,12 @@ def _stream_handle(stream):
 
 def make_opts(early_stop=True, check_from_iter=0, msg_fp16=False, llr_out_ptr=None,
               timing_events=None, checks_per_thread=0, schedule="auto",
-              streams=0) -> DecodeOpts:
+              streams=0, graphs=0) -> DecodeOpts:
     o = DecodeOpts()
     load().ldpc_decode_opts_init(ctypes.byref(o))
     o.checks_per_thread = int(checks_per_thread)
     o.streams = int(streams)
+    o.graphs = int(graphs)
     o.schedule = _SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.early_stop = int(bool(early_stop))
     o.check_from_iter = int(check_from_iter)
@@ -229,13 +230,15 @@ class Code:
 
     def decode(self, llr, syndrome, max_iters: int, early_stop=True, check_from_iter=0,
                msg_fp16=False, want_llr=False, workspace=None, out=None, stream=None,
-               timing_events=None, checks_per_thread=0, schedule="auto", streams=0):
+               timing_events=None, checks_per_thread=0, schedule="auto", streams=0, graphs=0):
         """Decode frames llr [F][n] float32 / syndrome [F][m] uint8 (CUDA tensors).
 
         Returns (bits uint8 [F][n], iters int32 [F], converged uint8 [F], L or None),
         all CUDA tensors, valid once ``stream`` (default: current) is synchronised.
         ``streams``: 0 library choice, 1 one stream, 2 two halves of the frames on
         two streams (per-iteration launches; as ldpc_decode_opts.streams).
+        ``graphs``: 0 replay repeated identical calls from a captured graph, 1
+        never (as ldpc_decode_opts.graphs).
         """
         import torch
         if llr.dtype != torch.float32 or syndrome.dtype != torch.uint8:
@@ -259,7 +262,7 @@ class Code:
             workspace = self.alloc_workspace(F, max_iters, msg_fp16, want_llr, dev)
         opts = make_opts(early_stop, check_from_iter, msg_fp16,
                          L.data_ptr() if L is not None else None, timing_events,
-                         checks_per_thread, schedule, streams)
+                         checks_per_thread, schedule, streams, graphs)
         st = load().ldpc_decode_batch(
             self._h, F, llr.data_ptr(), syndrome.data_ptr(), int(max_iters),
             bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ctypes.byref(opts),

@@ -293,6 +293,10 @@ def test_invalid_arguments(ldpc):
         with pytest.raises(ldpc.LdpcError) as err:
             g.decode(Q, s, 10, streams=bad)
         assert err.value.status == ldpc.LDPC_EINVAL
+    for bad in (-1, 2):
+        with pytest.raises(ldpc.LdpcError) as err:
+            g.decode(Q, s, 10, graphs=bad)
+        assert err.value.status == ldpc.LDPC_EINVAL
     with pytest.raises(ldpc.LdpcError):
         ldpc.Code(np.array([[0, Z]], dtype=np.int32), Z)
     with pytest.raises(ldpc.LdpcError):
@@ -377,6 +381,41 @@ def test_two_streams_match_one(ldpc, oracle_mod, Z, F):
         for name, a, b, c in zip(("bits", "iters", "converged", "llr"), two, one, timed):
             assert np.array_equal(a, b), (name, fp16)
             assert np.array_equal(a, c), (name, fp16)
+
+
+@pytest.mark.parametrize("streams", [1, 2])
+def test_repeated_decodes_replay_the_library_graph(ldpc, oracle_mod, streams):
+    """A decode repeated with the same sizes, options and pointers is captured
+    by the library at its second call and replayed from the third.  Every call
+    matches a decode that launches its kernels one by one (graphs=1) on the
+    same inputs, also after the inputs behind the same pointers change, FP32
+    and FP16.  Graphs serve one-stream decodes; with streams=2 every call
+    launches directly, and must match all the same."""
+    Z, F, T = 64, 6, 30
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    batches = []
+    for seed in (71, 72, 73):
+        x, Q = synth.biawgn_frames(g.n, F, -13.5, seed=seed)
+        batches.append((Q, o.syndrome(x)))
+    _say("library graph replay", Z, F, T, streams)
+    for fp16 in (False, True):
+        dQ, ds = _dev(batches[0][0]), _dev(batches[0][1])
+        ws = g.alloc_workspace(F, T, msg_fp16=fp16)
+        out = (torch.empty((F, g.n), dtype=torch.uint8, device="cuda"),
+               torch.empty(F, dtype=torch.int32, device="cuda"),
+               torch.empty(F, dtype=torch.uint8, device="cuda"), None)
+        for call, b in enumerate((0, 0, 1, 2, 0)):
+            dQ.copy_(_dev(batches[b][0]))
+            ds.copy_(_dev(batches[b][1]))
+            g.decode(dQ, ds, T, msg_fp16=fp16, workspace=ws, out=out, streams=streams)
+            torch.cuda.synchronize()
+            got = [t.cpu().numpy() for t in out[:3]]
+            ref = _gpu_decode(g, batches[b][0], batches[b][1], T, msg_fp16=fp16, streams=streams,
+                              graphs=1)
+            for name, u, v in zip(("bits", "iters", "converged"), got, ref[:3]):
+                assert np.array_equal(u, v), (name, fp16, call)
 
 
 @pytest.mark.parametrize("schedule", ["launches", "resident"])

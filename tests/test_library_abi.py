@@ -39,11 +39,11 @@ def test_status_strings_and_opts_defaults():
     assert lib.ldpc_status_string(0) == b"ok"
     assert lib.ldpc_status_string(-5).startswith(b"workspace")
     o = ldpc.DecodeOpts()
-    o.schedule, o.streams = 7, 7   # the last fields: init must reach them
+    o.schedule, o.streams, o.graphs = 7, 7, 7   # the last fields: init must reach them
     lib.ldpc_decode_opts_init(ctypes.byref(o))
     assert (o.early_stop, o.check_from_iter, o.msg_fp16, o.checks_per_thread, o.llr_out) == (1, 0, 0, 0, None)
     assert not o.timing_events and o.n_timing_events == 0
-    assert (o.schedule, o.streams) == (0, 0)
+    assert (o.schedule, o.streams, o.graphs) == (0, 0, 0)
     # host-only argument checks fail before any device call
     h = ctypes.c_void_p()
     assert lib.ldpc_code_create(1, 1, None, 4, ctypes.byref(h)) == ldpc.LDPC_EINVAL
