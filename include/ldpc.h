@@ -15,8 +15,12 @@
  *  - Memory: pointers named "device" must point into HIP device memory of the
  *    device the code was created on (e.g. torch CUDA tensors); "host" pointers
  *    are ordinary host memory.  The caller owns every data buffer and the
- *    workspace; the library owns only the code handle and its small device
- *    tables, and performs no device allocation inside ldpc_decode_batch.
+ *    workspace; the library owns the code handle, its small device tables, two
+ *    streams of its own with their events, and up to 4 decode graphs.  Inside
+ *    ldpc_decode_batch the only allocation is the one the HIP runtime makes
+ *    when a repeated small decode is captured into a graph (see
+ *    ldpc_decode_opts.graphs; graphs = 1 avoids it, and
+ *    ldpc_decode_batch_noalloc never makes graphs).
  *  - Streams: decode and syndrome calls are asynchronous on the given
  *    hipStream_t (NULL = the null stream); outputs are valid after the caller
  *    synchronises that stream.  Launch errors are reported at enqueue; faults
