@@ -418,6 +418,34 @@ def test_repeated_decodes_replay_the_library_graph(ldpc, oracle_mod, streams):
                 assert np.array_equal(u, v), (name, fp16, call)
 
 
+def test_library_graphs_evict_and_alternate(ldpc, oracle_mod):
+    """The code handle keeps 4 graphs, least recently used replaced.  Five
+    calls of different workspaces in turn keep evicting each other (no key
+    reaches its second call while cached); then two alternating calls are
+    both captured and replayed.  Every output matches direct launches."""
+    Z, F, T = 64, 3, 20
+    base = synth.template_base(144, Z, seed=1)
+    g = ldpc.Code(base, Z)
+    o = oracle_mod.OracleCode(base, Z)
+    x, Q = synth.biawgn_frames(g.n, F, -13.5, seed=81)
+    s = o.syndrome(x)
+    dQ, ds = _dev(Q), _dev(s)
+    ref = _gpu_decode(g, Q, s, T, graphs=1)
+    wss = [g.alloc_workspace(F, T) for _ in range(5)]
+    outs = [(torch.empty((F, g.n), dtype=torch.uint8, device="cuda"),
+             torch.empty(F, dtype=torch.int32, device="cuda"),
+             torch.empty(F, dtype=torch.uint8, device="cuda"), None) for _ in range(5)]
+    _say("library graph eviction", Z, F, T)
+    order = [0, 1, 2, 3, 4] * 3 + [0, 1] * 4
+    for call, k in enumerate(order):
+        for t in outs[k][:3]:
+            t.fill_(7)
+        g.decode(dQ, ds, T, workspace=wss[k], out=outs[k])
+        torch.cuda.synchronize()
+        for name, u, v in zip(("bits", "iters", "converged"), outs[k][:3], ref[:3]):
+            assert np.array_equal(u.cpu().numpy(), v), (name, call, k)
+
+
 @pytest.mark.parametrize("schedule", ["launches", "resident"])
 def test_decode_replays_from_a_captured_graph(ldpc, oracle_mod, schedule):
     """A whole decode (caller-owned workspace and outputs) captured by stream
